@@ -1,0 +1,87 @@
+"""Pins of the oracle's whitening (Section 3.1 and Section 4.2).
+
+* closed form: on an exact rank-k M2 the randomized whitener equals the
+  definition W = U_M2 Sigma_M2^(-1/2) computed from a dense eigendecomposition
+  of the explicit M2 (same sign rule), and W^T M2 W = I;
+* the whitened samples are the definition y = W^T c / l, checked row by row.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from planted import exact_m2, planted_topics
+
+
+@pytest.mark.parametrize("d,k", [(12, 3), (40, 7), (200, 10)])
+def test_whitener_exact_rank_k(d, k):
+    mu, ahat = planted_topics(d, k, seed=d + k)
+    M2 = exact_m2(mu, ahat)
+    S = synth.projection(d, 2 * k, seed=7)
+    W, evals = oracle.whitener_rsvd(M2 @ S, S, k)
+    np.testing.assert_allclose(W.T @ M2 @ W, np.eye(k), atol=1e-12)
+    # the definition of Section 3.1 through a dense eigendecomposition
+    lam, U = np.linalg.eigh(M2)
+    order = np.argsort(-lam)[:k]
+    W_def = oracle.canonical_signs(U[:, order] / np.sqrt(lam[order])[None, :])
+    np.testing.assert_allclose(W, W_def, atol=1e-10 * np.abs(W_def).max())
+    np.testing.assert_allclose(evals, lam[order], rtol=1e-11)
+
+
+def test_whitener_projection_size_independent():
+    """Nystrom with any k_tilde >= k recovers the same W on an exact rank-k M2."""
+    mu, ahat = planted_topics(30, 4, seed=9)
+    M2 = exact_m2(mu, ahat)
+    Ws = []
+    for kt in (4, 8, 13):
+        S = synth.projection(30, kt, seed=kt)
+        Ws.append(oracle.whitener_rsvd(M2 @ S, S, 4)[0])
+    np.testing.assert_allclose(Ws[0], Ws[1], atol=1e-10)
+    np.testing.assert_allclose(Ws[0], Ws[2], atol=1e-10)
+
+
+def test_whitener_rejects_indefinite():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((10, 10))
+    M2 = -(A @ A.T)
+    S = synth.projection(10, 6, seed=1)
+    with pytest.raises(oracle.NotPSDError):
+        oracle.whitener_rsvd(M2 @ S, S, 3)
+
+
+def test_canonical_signs_rule():
+    W = np.array([[1.0, -3.0, 2.0], [-2.0, 1.0, -2.0], [0.5, 2.9, 1.0]])
+    V = oracle.canonical_signs(W)
+    np.testing.assert_array_equal(V[:, 0], [-1.0, 2.0, -0.5])
+    np.testing.assert_array_equal(V[:, 1], [3.0, -1.0, -2.9])
+    np.testing.assert_array_equal(V[:, 2], [2.0, -2.0, 1.0])   # tie: lowest row wins
+
+
+def test_whiten_rows_definition():
+    inst = synth.lda(d=15, k=2, alpha0=1.0, beta=0.5, n_docs=30, mean_len=9.0, seed=4)
+    W = synth.projection(15, 4, seed=2)
+    for v in inst.views:
+        Y, ybar = oracle.whiten(v, W, normalize=True)
+        dense = v.to_scipy(np.float64).toarray()
+        for t in range(dense.shape[0]):
+            np.testing.assert_allclose(Y[t], W.T @ dense[t] / dense[t].sum(), atol=1e-14)
+        np.testing.assert_allclose(ybar, Y.sum(0) / Y.shape[0], atol=1e-15)
+    g = synth.mmsb(n=50, k=2, alpha0=0.3, p=0.5, q=0.1, n_x=25, seed=1)
+    Wg = synth.projection(g.C.n_cols, 3, seed=5)
+    Y, _ = oracle.whiten(g.C, Wg, normalize=False)
+    np.testing.assert_allclose(Y, g.C.to_scipy(np.float64).toarray() @ Wg, atol=1e-13)
+
+
+def test_sampled_graph_whitener_invariant_on_low_rank_m2():
+    """On sampled data W whitens the Nystrom approximation O Omega^+ O^T
+    restricted to its top k (the matrix it is built from)."""
+    g = synth.mmsb(n=400, k=4, alpha0=0.2, p=0.5, q=0.05, n_x=200, seed=3)
+    S = synth.projection(g.C.n_cols, 8, seed=9)
+    O = oracle.m2_apply(g.C, S, 0.2, normalize=False)
+    W, _ = oracle.whitener_rsvd(O, S, 4)
+    Om = S.T @ O
+    Om = 0.5 * (Om + Om.T)
+    sig, U = np.linalg.eigh(Om)
+    idx = np.argsort(-sig)[:4]
+    B = O @ U[:, idx] / np.sqrt(sig[idx])
+    np.testing.assert_allclose(W.T @ (B @ B.T) @ W, np.eye(4), atol=1e-11)
