@@ -16,7 +16,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "NotPSDError", "as_sparse", "row_weights", "dirichlet_coefficients", "first_moment",
-    "m2_apply", "whitener_rsvd", "canonical_signs", "whiten", "sgd_step", "sgd_direction",
+    "m2_apply", "power_sketch", "whitener_rsvd", "canonical_signs", "whiten", "sgd_step", "sgd_direction",
     "sgd_run", "beta_schedule", "steps_per_pass", "whitened_tensor", "residual",
     "unwhiten_topics", "recover_pi", "eigen_from_factors",
 ]
@@ -92,6 +92,23 @@ def m2_apply(C, S: np.ndarray, alpha0: float, normalize: bool) -> np.ndarray:
     pair = Cs.T @ (w2[:, None] * CS)
     diag = np.asarray(Cs.T @ w2).ravel()[:, None] * S
     return (alpha0 + 1.0) / n * (pair - diag) - alpha0 * np.outer(M1, M1 @ S)
+
+
+def power_sketch(C, S: np.ndarray, alpha0: float, normalize: bool, q: int):
+    """Sketch of M2 for the whitener with q power iterations.
+
+    READING (Section 4.2 on sampled data): the Nystrom step needs
+    S^T M2 S to be positive definite on its top k eigenpairs, which fails for
+    sampled moments whose many small noise eigenvalues (of both signs) swamp a
+    sketch of width 2k.  The sketch is therefore refined by
+    Q_0 = S, Q_j = orth(M2 Q_{j-1}) (a basis of the span; QR here), the power
+    method sketch of the Nystrom analysis the paper cites; q = 0 is the
+    paper's algorithm.  Returns (Q_q, O = M2 Q_q) for whitener_rsvd(O, Q_q, k).
+    """
+    Q = S
+    for _ in range(q):
+        Q = np.linalg.qr(m2_apply(C, Q, alpha0, normalize))[0]
+    return Q, m2_apply(C, Q, alpha0, normalize)
 
 
 def canonical_signs(W: np.ndarray) -> np.ndarray:

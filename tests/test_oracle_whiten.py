@@ -40,6 +40,40 @@ def test_whitener_projection_size_independent():
     np.testing.assert_allclose(Ws[0], Ws[2], atol=1e-10)
 
 
+@pytest.mark.parametrize("q", [1, 3])
+def test_power_sketch_exact_rank_k_gives_the_definition(q):
+    """Power iterations keep an exact rank-k M2's whitener: W = U Sigma^(-1/2)."""
+    d, k = 60, 5
+    mu, ahat = planted_topics(d, k, seed=17)
+    M2 = exact_m2(mu, ahat)
+    S = synth.projection(d, 2 * k, seed=3)
+    Q = S
+    for _ in range(q):
+        Q = np.linalg.qr(M2 @ Q)[0]
+    W, _ = oracle.whitener_rsvd(M2 @ Q, Q, k)
+    lam, U = np.linalg.eigh(M2)
+    order = np.argsort(-lam)[:k]
+    W_def = oracle.canonical_signs(U[:, order] / np.sqrt(lam[order])[None, :])
+    np.testing.assert_allclose(W, W_def, atol=1e-9 * np.abs(W_def).max())
+
+
+def test_power_sketch_repairs_indefinite_projection():
+    """Sampled graph moment: the plain width-2k sketch is indefinite at rank k,
+    three power iterations make it definite and the whitener is then as good
+    as the dense top-k eigendecomposition of the same M2."""
+    g = synth.make("mmsb_small")
+    k = 10
+    S = synth.projection(g.C.n_cols, 2 * k, seed=1)
+    with pytest.raises(oracle.NotPSDError):
+        oracle.whitener_rsvd(oracle.m2_apply(g.C, S, 0.1, False), S, k)
+    Q, O = oracle.power_sketch(g.C, S, 0.1, False, 3)
+    W, ev = oracle.whitener_rsvd(O, Q, k)
+    M2 = oracle.m2_apply(g.C, np.eye(g.C.n_cols), 0.1, False)
+    lam = np.sort(np.linalg.eigvalsh(M2))[::-1][:k]
+    np.testing.assert_allclose(ev, lam, rtol=0.05)
+    np.testing.assert_allclose(W.T @ M2 @ W, np.eye(k), atol=0.1)
+
+
 def test_whitener_rejects_indefinite():
     rng = np.random.default_rng(0)
     A = rng.standard_normal((10, 10))
