@@ -1,0 +1,235 @@
+/*
+ * otm.h -- C ABI of the MI355X (gfx950) hot path of the online tensor method
+ * for latent variable models (Huang, Niranjan, Hakeem, Anandkumar, "Online
+ * Tensor Methods for Learning Latent Variable Models").
+ *
+ * Path: M2 operator -> randomized whitener -> whitening SpMM -> stochastic
+ * tensor gradient descent (STGD) on the implicit whitened third moment ->
+ * post-processing (topics / memberships).
+ *
+ * Conventions (every entry point):
+ *  - Array arguments are DEVICE pointers owned by the caller, unless noted.
+ *    The library never allocates device memory: scratch space comes from the
+ *    caller through (ws, ws_bytes); query its size with the matching
+ *    *_workspace function.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns after host-side validation; results are visible after
+ *    the stream is synchronised.  Conditions that depend on device data (an
+ *    indefinite moment, a non-finite update) are reported through device
+ *    flags named in each entry point.
+ *  - Return value: OTM_OK or a negative otm_status; otm_last_error() then
+ *    holds a message (thread-local).  No exception crosses the ABI and the
+ *    library never aborts the process.
+ *  - Dense row-major layout.  A factor matrix Phi (k x k) stores phi_i, the
+ *    i-th estimated eigenvector, contiguously at Phi + i*k.
+ *  - Results do not depend on run-to-run scheduling: all reductions use a
+ *    fixed order and no floating-point atomics.
+ */
+#ifndef OTM_H
+#define OTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OTM_OK = 0,
+    OTM_EINVAL = -1,      /* null pointer or invalid scalar argument */
+    OTM_ESHAPE = -2,      /* inconsistent sizes */
+    OTM_EDTYPE = -3,      /* unsupported element type for this entry point */
+    OTM_ENOTPSD = -4,     /* projected second moment has no k positive eigenvalues */
+    OTM_ENONFINITE = -5,  /* a non-finite value was produced */
+    OTM_EHIP = -6,        /* HIP runtime error */
+    OTM_EWORKSPACE = -7,  /* workspace missing or too small */
+    OTM_ECAPACITY = -8    /* size beyond the compiled capacity (see otm_max_k) */
+} otm_status;
+
+typedef enum { OTM_F64 = 0, OTM_F32 = 1, OTM_BF16 = 2 } otm_dtype;
+
+typedef void* otm_stream; /* hipStream_t */
+
+/* Sparse observations in CSR form (Sections 2.1-2.2: word counts c_t of a
+ * document, or the adjacency row G[x, A] of a node).  Device arrays:
+ * rowptr (n_rows + 1), colidx (nnz, each < n_cols), vals (nnz; NULL means
+ * every stored entry is 1).  Kernels skip entries whose column is out of
+ * range and clamp row ranges to [0, nnz], so malformed input cannot make
+ * them read out of bounds; otm_csr_check reports it. */
+typedef struct {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    const float* vals;
+} otm_csr;
+
+const char* otm_status_string(int status);
+const char* otm_last_error(void);
+int otm_version(void);
+/* Largest k (number of components) the STGD kernels are compiled for. */
+int otm_max_k(void);
+/* Largest mini-batch of the STGD kernels. */
+int otm_max_batch(void);
+
+/* Validates a CSR on the device and synchronises `stream`: rowptr[0] == 0,
+ * non-decreasing, rowptr[n_rows] == nnz, every colidx in [0, n_cols).
+ * *bad_count receives the number of violations (0 = valid).  ws must hold
+ * otm_csr_check_workspace() bytes. */
+size_t otm_csr_check_workspace(void);
+int otm_csr_check(const otm_csr* C, int64_t* bad_count, void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- a1: second-moment operator (Section 2, Eq. 2moment; Section 4.2) -----
+ * O = M2 S for the n x d observations C, without forming M2:
+ *   M2 = (alpha0+1)/n sum_t w2_t (c_t c_t^T - diag c_t) - alpha0 M1 M1^T,
+ *   M1 = (1/n) sum_t w1_t c_t.
+ * normalize != 0 (documents): w1_t = 1/l_t, w2_t = 1/(l_t (l_t - 1)) with l_t
+ * the row sum (every row needs l_t >= 2, else *info = 1 and O is undefined);
+ * normalize == 0 (graph rows): w1 = w2 = 1.
+ * C: n x d; CT: its transpose (d x n) with the same entries.
+ * S: d x k_tilde FP64 row-major (the random projection).  O: d x k_tilde FP64.
+ * info: device int32, set to 0 on success.  FP64 throughout. */
+size_t otm_m2_apply_workspace(int32_t n, int32_t d, int32_t k_tilde);
+int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, double alpha0,
+                 const double* S, int32_t k_tilde, double* O, int32_t* info,
+                 void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- a2: randomized whitener (Section 3.1; Section 4.2, "Randomized
+ * Tall-thin SVD" and its tall-thin QR variant) -----------------------------
+ * From O = M2 S (d x k_tilde) and S (d x k_tilde), FP64:
+ *   Omega = sym(S^T O) = U diag(sigma) U^T (sigma descending),
+ *   B = O U_k diag(sigma_k)^(-1/2),   B = U_B diag(s) V_B^T,
+ *   W = U_B diag(s)^(-1)     so that W^T (B B^T) W = I,
+ * columns sign-fixed so that each column's largest-magnitude entry is
+ * positive (ties: lowest row).  W: d x k FP64; evals: k FP64 (s^2, the top
+ * eigenvalues of the low-rank M2).  W_lo: optional (may be NULL) copy of W in
+ * w_lo_dtype (OTM_F32 or OTM_BF16, round-to-nearest-even) for otm_whiten.
+ * info: device int32, 0 on success, 1 if sigma_k <= 1e-12 sigma_1 or
+ * sigma_k <= 0 (OTM_ENOTPSD condition; W undefined).  k <= k_tilde <= 256. */
+size_t otm_whitener_workspace(int32_t d, int32_t k_tilde, int32_t k);
+int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, int32_t k,
+                 double* W, double* evals, void* W_lo, int w_lo_dtype, int32_t* info,
+                 void* ws, size_t ws_bytes, otm_stream stream);
+
+/* Orthonormal basis of the sketch for power iterations (READING of Section
+ * 4.2 for sampled data: the projected moment S^T M2 S is indefinite at
+ * k_tilde = 2k when M2's noise directions dominate the sketch, so the sketch
+ * is refined by q steps Q <- orth(M2 Q) before the whitener, as in the power
+ * method sketches of the cited Nystrom analysis; q = 0 is the paper's
+ * algorithm).  Q = Y (Y^T Y)^(-1/2), d x m FP64, via a Jacobi eigensolver of
+ * the m x m Gram.  info: device int32, 0 on success, 1 if Y is rank deficient
+ * (Gram eigenvalue <= 1e-14 of the largest).  m <= min(d, 256); Y, Q must not
+ * alias. */
+size_t otm_orthonormalize_workspace(int32_t d, int32_t m);
+int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double* Q, int32_t* info,
+                       void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- a3: whitening SpMM (Section 3.1 whitened data; Appendix A) ----------
+ * Y[t, :] = r_t * sum_j C[t, j] W[j, :],  r_t = 1 / (row sum) if normalize
+ * (document views) else 1.  W: n_cols x k row-major in w_dtype (OTM_F32 or
+ * OTM_BF16).  Y: n_rows x ldy row-major in y_dtype (OTM_F32 or OTM_BF16,
+ * round-to-nearest-even), FP32 accumulation; columns k..ldy-1 are written
+ * with 0.  ldy >= k; ldy % 8 == 0 for OTM_BF16, ldy % 4 == 0 for OTM_F32.
+ * ybar: optional (NULL allowed) k floats, the mean of Y's rows computed from
+ * the FP32 accumulators (Appendix A: ybar = E_t[y_t]), fixed-order sum.
+ * A row with sum 0 under normalize gives a zero row. */
+size_t otm_whiten_workspace(int32_t n_rows, int32_t k);
+int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k,
+               void* Y, int y_dtype, int32_t ldy, float* ybar,
+               void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- a4 / a5: stochastic tensor gradient descent (Section 3.2, Lemma
+ * "update"; stacked form of Section 4.3) -----------------------------------
+ * For a batch of rows t with whitened views yA_t, yB_t, yC_t (rows of YA,
+ * YB, YC; n x ldy row-major, y_dtype OTM_F32 or OTM_BF16; the three may alias)
+ * and global means ybar (3 x k FP32: ybar_A, ybar_B, ybar_C), every phi_i
+ * moves by beta * Delta_i where Delta_i is the batch mean of
+ *   -kappa sum_j <phi_j,phi_i>^2 phi_j
+ *   + a <phi_i,yA><phi_i,yB> yC + c <phi_i,ybarA><phi_i,ybarB> ybarC
+ *   - b (<phi_i,yA><phi_i,yB> ybarC + <phi_i,yA><phi_i,ybarB> yC
+ *        + <phi_i,ybarA><phi_i,yB> yC),
+ * a = (alpha0+1)(alpha0+2)/2, b = alpha0(alpha0+1)/2, c = alpha0^2,
+ * kappa = (1+theta)/2.  All k components update from the same old Phi.
+ * Contractions run on the matrix cores: FP32 inputs in FP32, BF16 inputs in
+ * BF16 with FP32 accumulation; the FP32 master copy of Phi is updated with
+ * compensated (Kahan) summation when compensated != 0.
+ * Capacity: k <= otm_max_k(), batch <= otm_max_batch(). */
+typedef struct {
+    int32_t k;          /* components */
+    int32_t batch;      /* mini-batch size B */
+    int32_t passes;     /* passes over the data (rows of perms) */
+    int32_t ldy;        /* row stride of YA/YB/YC in elements */
+    int32_t y_dtype;    /* OTM_F32 or OTM_BF16 */
+    int32_t compensated;
+    double alpha0;
+    double theta;       /* orthogonality weight, 1 in the paper's experiments */
+    double beta0;       /* beta_t = beta0 / (1 + t / beta_tau), t the global step */
+    double beta_tau;
+} otm_sgd_params;
+
+/* One step on the first `rows` rows of YA/YB/YC (1 <= rows <= batch) with
+ * rate beta.  Phi (k x k FP32) is updated in place; Phi_comp: NULL or the
+ * k x k compensation terms, read and written. */
+int otm_sgd_step(const otm_sgd_params* p, int32_t rows, const void* YA, const void* YB,
+                 const void* YC, const float* ybar, double beta, float* Phi, float* Phi_comp,
+                 otm_stream stream);
+
+/* Global steps [start_step, end_step) of an online run over n rows:
+ * step t is pass t / S, batch t % S, S = ceil(n / batch); pass p visits rows
+ * perms[p*n + 0 .. n-1] (perms: passes x n int32, a permutation of 0..n-1 per
+ * pass; NULL visits rows in order), the last batch of a pass holding the
+ * remaining n - (S-1)*batch rows.  end_step < 0 means passes * S.
+ * `restarts` independent runs execute concurrently, one per workgroup: run r
+ * uses Phi + r*k*k, Phi_comp + r*k*k (if not NULL), perms + r*perm_stride and
+ * writes snapshots + r*passes*k*k.  snapshots: NULL or restarts x passes x
+ * k x k, Phi after the last step of each pass.  nonfinite: NULL or a device
+ * int32 that is set to 1 (never cleared) if an update is not finite or a
+ * permutation entry lies outside [0, n) (that entry then reads row 0). */
+int otm_sgd_run(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB,
+                const void* YC, const float* ybar, const int32_t* perms, int64_t perm_stride,
+                int32_t restarts, int64_t start_step, int64_t end_step, float* Phi,
+                float* Phi_comp, float* snapshots, int32_t* nonfinite, otm_stream stream);
+
+/* ---- a6: post-processing (Section 3.3, Lemma "postprocessing") -----------
+ * lambda_i = kappa ||phi_i||^3, u_i = phi_i / ||phi_i||,
+ * mu_i = lambda_i (W^T)^+ u_i with (W^T)^+ = W (W^T W)^(-1), negatives
+ * clipped to 0, columns normalised to sum 1 (a zero column stays 0);
+ * alpha_hat_i = lambda_i^(-2) / sum_j lambda_j^(-2).
+ * W: d x k FP64; Phi: k x k FP32; mu: d x k FP64 row-major; alpha_hat, lambda:
+ * k FP64.  info: device int32, 0 on success, 1 if W^T W is not positive
+ * definite.  FP64 throughout. */
+size_t otm_unwhiten_workspace(int32_t d, int32_t k);
+int otm_unwhiten_topics(const double* W, int32_t d, int32_t k, const float* Phi, double theta,
+                        double* mu, double* alpha_hat, double* lambda, int32_t* info,
+                        void* ws, size_t ws_bytes, otm_stream stream);
+
+/* Memberships of the n samples (Lemma postprocessing with unit eigenvectors):
+ * Pi[:, x] = diag(lambda)^(-1) U^T y_x, then negatives clipped to 0, column
+ * normalised to sum 1, entries < tau set to 0, normalised again (a column
+ * summing to 0 stays 0).  Y: n x ldy in y_dtype (OTM_F32 or OTM_BF16);
+ * Phi: k x k FP32; Pi: k x n FP32 row-major.  FP64 arithmetic. */
+size_t otm_recover_pi_workspace(int32_t k);
+int otm_recover_pi(const void* Y, int y_dtype, int32_t ldy, int32_t n, int32_t k,
+                   const float* Phi, double theta, double tau, float* Pi,
+                   void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- loss (measurement only; the hot path never forms the tensor) --------
+ * T (k x k x k FP64, T[(a*k + b)*k + c]) = the whitened tensor of Section
+ * 3.2:  a/n sum_t yA x yB x yC - b/n sum_t (yA x yB x ybarC + yA x ybarB x yC
+ * + ybarA x yB x yC) + c ybarA x ybarB x ybarC, over all n rows. */
+int otm_tensor_form(const void* YA, const void* YB, const void* YC, int y_dtype, int32_t ldy,
+                    int32_t n, int32_t k, const float* ybar, double alpha0, double* T,
+                    otm_stream stream);
+/* R[j] = ||sum_i phi_i^(x3) - T||_F^2 / ||T||_F^2 for `count` factor
+ * matrices Phi + j*k*k (FP32), FP64 arithmetic.  R: count doubles. */
+size_t otm_residual_workspace(int32_t k, int32_t count);
+int otm_residual(const double* T, int32_t k, const float* Phi, int32_t count, double* R,
+                 void* ws, size_t ws_bytes, otm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OTM_H */

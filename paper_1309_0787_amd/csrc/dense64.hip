@@ -1,0 +1,599 @@
+// FP64 dense linear algebra of the whitening and post-processing steps.
+//
+//  * gemm_tn: C = A^T B for tall A, B (d x p, d x q): split-K partials over row
+//    chunks, then a fixed-order reduction.
+//  * gemm_nn: C = A B with A tall (d x p) and B small (p x q).
+//  * jacobi: cyclic two-sided Jacobi eigensolver for a symmetric n x n matrix
+//    (n <= 256) in one workgroup.  Rounds follow the round-robin tournament
+//    order, so each round applies n/2 disjoint rotations at once: every 2x2
+//    block (rows of pair P, columns of pair Q) becomes R_P^T X R_Q, and the
+//    eigenvector matrix's column pairs rotate by R_P.  A pair is rotated only
+//    while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and |a_pq| > 1e-18 ||A||_F; sweeps
+//    stop after one without any rotation (at most 60).
+//  * whitener (Section 3.1; Section 4.2, randomized tall-thin SVD with the
+//    projected matrix truncated to its top k eigenpairs):
+//      Omega = sym(S^T O) -> eig -> B = O U_k sigma_k^(-1/2)
+//      B^T B = V_B diag(s^2) V_B^T -> W = B V_B diag(s^-2) = U_B diag(s)^-1
+//      and every column of W turned so that its largest |entry| is positive.
+//  * orthonormalize: Q = Y (Y^T Y)^(-1/2), an orthonormal basis of span(Y), for
+//    the power iterations of the sketch.
+//  * unwhiten_topics (Lemma postprocessing).
+#include <cmath>
+
+#include "otm_internal.h"
+
+namespace otm {
+namespace {
+
+// ------------------------------------------------------------------ gemm_tn
+constexpr int kTnTile = 32;
+constexpr int kTnRows = 16;
+
+__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(const double* __restrict__ A, int lda,
+                                                              const double* __restrict__ B, int ldb, int d, int p,
+                                                              int q, int chunk, double* __restrict__ part) {
+    __shared__ double sA[kTnRows][kTnTile + 1];
+    __shared__ double sB[kTnRows][kTnTile + 1];
+    const int p0 = blockIdx.x * kTnTile, q0 = blockIdx.y * kTnTile;
+    const int r0 = blockIdx.z * chunk, r1 = min(d, r0 + chunk);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // thread owns (p0+2ty+{0,1}, q0+2tx+{0,1})
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int rb = r0; rb < r1; rb += kTnRows) {
+        for (int e = threadIdx.x; e < kTnRows * kTnTile; e += 256) {
+            const int rr = e / kTnTile, cc = e % kTnTile;
+            const int r = rb + rr;
+            sA[rr][cc] = (r < r1 && p0 + cc < p) ? A[(size_t)r * lda + p0 + cc] : 0.0;
+            sB[rr][cc] = (r < r1 && q0 + cc < q) ? B[(size_t)r * ldb + q0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < kTnRows; ++rr) {
+            const double a0 = sA[rr][2 * ty], a1 = sA[rr][2 * ty + 1];
+            const double b0 = sB[rr][2 * tx], b1 = sB[rr][2 * tx + 1];
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
+        }
+        __syncthreads();
+    }
+    double* out = part + (size_t)blockIdx.z * p * q;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int pi = p0 + 2 * ty + i, qj = q0 + 2 * tx + j;
+            if (pi < p && qj < q) out[(size_t)pi * q + qj] = acc[i][j];
+        }
+}
+
+__global__ void reduce_parts_kernel(const double* __restrict__ part, int nparts, int64_t m, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[(size_t)b * m + i];
+    out[i] = s;
+}
+
+int tn_chunks(int d) {
+    int c = (d + 511) / 512;
+    return c < 1 ? 1 : (c > 64 ? 64 : c);
+}
+
+size_t gemm_tn_ws(int d, int p, int q) { return ws_round(sizeof(double) * (size_t)tn_chunks(d) * p * q); }
+
+int gemm_tn(const double* A, int lda, const double* B, int ldb, int d, int p, int q, double* C, double* part,
+            hipStream_t s) {
+    const int nch = tn_chunks(d);
+    const int chunk = (d + nch - 1) / nch;
+    dim3 grid((p + kTnTile - 1) / kTnTile, (q + kTnTile - 1) / kTnTile, nch);
+    hipLaunchKernelGGL(gemm_tn_partial_kernel, grid, dim3(256), 0, s, A, lda, B, ldb, d, p, q, chunk, part);
+    int st = check_launch("gemm_tn_partial_kernel");
+    if (st != OTM_OK) return st;
+    const int64_t m = (int64_t)p * q;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, part, nch, m, C);
+    return check_launch("reduce_parts_kernel");
+}
+
+// ------------------------------------------------------------------ gemm_nn
+constexpr int kNnM = 64, kNnN = 64, kNnK = 16;
+
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                                      int ldb, double* __restrict__ C, int ldc, int d, int p, int q) {
+    __shared__ double sA[kNnK][kNnM + 1];
+    __shared__ double sB[kNnK][kNnN + 1];
+    const int r0 = blockIdx.x * kNnM, c0 = blockIdx.y * kNnN;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // rows r0+ty+16i, cols c0+tx+16j
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < p; k0 += kNnK) {
+        for (int e = threadIdx.x; e < kNnK * kNnM; e += 256) {
+            const int rr = e / kNnK, kk = e % kNnK;
+            const int r = r0 + rr, kx = k0 + kk;
+            sA[kk][rr] = (r < d && kx < p) ? A[(size_t)r * lda + kx] : 0.0;
+        }
+        for (int e = threadIdx.x; e < kNnK * kNnN; e += 256) {
+            const int kk = e / kNnN, cc = e % kNnN;
+            const int kx = k0 + kk, c = c0 + cc;
+            sB[kk][cc] = (kx < p && c < q) ? B[(size_t)kx * ldb + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kNnK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = sA[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = sB[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+            if (r < d && c < q) C[(size_t)r * ldc + c] = acc[i][j];
+        }
+}
+
+int gemm_nn(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int d, int p, int q,
+            hipStream_t s) {
+    dim3 grid((d + kNnM - 1) / kNnM, (q + kNnN - 1) / kNnN);
+    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, d, p, q);
+    return check_launch("gemm_nn_kernel");
+}
+
+// ------------------------------------------------------------------- jacobi
+constexpr int kJacThreads = 1024;
+constexpr int kJacMaxN = 256;
+
+__device__ __forceinline__ int rr_player(int pos, int round, int N) {
+    if (pos == 0) return 0;
+    return 1 + (pos - 1 + round) % (N - 1);
+}
+
+// A (n x n, symmetric, overwritten), V (n x n, set to the eigenvectors as columns).
+// On exit evals[i] = A[i][i] and order[j] = index of the j-th largest eigenvalue
+// (ties: lower index first).
+__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n,
+                                                             double* __restrict__ evals, int* __restrict__ order) {
+    __shared__ double sc[kJacMaxN / 2], ss[kJacMaxN / 2];
+    __shared__ int sp[kJacMaxN / 2], sq[kJacMaxN / 2];
+    __shared__ double s_red[kJacThreads / 64];
+    __shared__ double s_fro;
+    __shared__ int s_rotated;
+    const int tid = threadIdx.x;
+    const int N = (n + 1) & ~1;           // even count; index n (if n odd) is a dummy
+    const int npairs = N / 2;
+    // Frobenius norm (invariant under the rotations) for the absolute threshold
+    double f = 0.0;
+    for (int e = tid; e < n * n; e += kJacThreads) {
+        V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+        f += A[e] * A[e];
+    }
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
+    if ((tid & 63) == 0) s_red[tid >> 6] = f;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kJacThreads / 64; ++w) t += s_red[w];
+        s_fro = sqrt(t);
+    }
+    __syncthreads();
+    const double abs_tol = 1e-18 * s_fro;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) s_rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < N - 1; ++round) {
+            if (tid < npairs) {
+                int p = rr_player(tid, round, N), q = rr_player(N - 1 - tid, round, N);
+                if (p > q) { const int t = p; p = q; q = t; }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q], apq = A[(size_t)p * n + q];
+                    const bool small = fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= abs_tol;
+                    if (!small) {
+                        const double theta = (aqq - app) / (2.0 * apq);
+                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                        s_rotated = 1;
+                    }
+                }
+                sp[tid] = p;
+                sq[tid] = q;
+                sc[tid] = c;
+                ss[tid] = s;
+            }
+            __syncthreads();
+            // two-sided update on 2x2 blocks
+            for (int e = tid; e < npairs * npairs; e += kJacThreads) {
+                const int P = e / npairs, Q = e % npairs;
+                const int p1 = sp[P], q1 = sq[P], p2 = sp[Q], q2 = sq[Q];
+                const double c1 = sc[P], s1 = ss[P], c2 = sc[Q], s2 = ss[Q];
+                if (s1 == 0.0 && s2 == 0.0) continue;
+                const bool r1ok = q1 < n, r2ok = q2 < n;   // p < q, so only q can be the dummy
+                const double x00 = A[(size_t)p1 * n + p2];
+                const double x01 = r2ok ? A[(size_t)p1 * n + q2] : 0.0;
+                const double x10 = r1ok ? A[(size_t)q1 * n + p2] : 0.0;
+                const double x11 = (r1ok && r2ok) ? A[(size_t)q1 * n + q2] : 0.0;
+                // R = [[c, s], [-s, c]];  X' = R1^T X R2
+                const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
+                const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
+                A[(size_t)p1 * n + p2] = y00 * c2 - y01 * s2;
+                if (r2ok) A[(size_t)p1 * n + q2] = y00 * s2 + y01 * c2;
+                if (r1ok) A[(size_t)q1 * n + p2] = y10 * c2 - y11 * s2;
+                if (r1ok && r2ok) A[(size_t)q1 * n + q2] = y10 * s2 + y11 * c2;
+            }
+            // eigenvector columns
+            for (int e = tid; e < n * npairs; e += kJacThreads) {
+                const int r = e / npairs, P = e % npairs;
+                const int p1 = sp[P], q1 = sq[P];
+                const double c = sc[P], s = ss[P];
+                if (s == 0.0 || q1 >= n) continue;
+                const double vp = V[(size_t)r * n + p1], vq = V[(size_t)r * n + q1];
+                V[(size_t)r * n + p1] = c * vp - s * vq;
+                V[(size_t)r * n + q1] = s * vp + c * vq;
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        if (!s_rotated) break;     // a whole sweep without a rotation: converged
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += kJacThreads) evals[i] = A[(size_t)i * n + i];
+    __syncthreads();
+    for (int i = tid; i < n; i += kJacThreads) {
+        const double v = evals[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double u = evals[j];
+            if (u > v || (u == v && j < i)) ++rank;
+        }
+        order[rank] = i;
+    }
+}
+
+int jacobi(double* A, double* V, int n, double* evals, int* order, hipStream_t s) {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacThreads), 0, s, A, V, n, evals, order);
+    return check_launch("jacobi_kernel");
+}
+
+// ---------------------------------------------------------------- whitener
+__global__ void symmetrize_kernel(double* __restrict__ A, int n) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, j = e % n;
+    if (i < j) {
+        const double m = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+        A[(size_t)i * n + j] = m;
+        A[(size_t)j * n + i] = m;
+    }
+}
+
+// Pk[:, j] = V[:, order[j]] / sqrt(sigma_order[j]), j < k;  info = 1 if sigma_k not positive enough
+__global__ void top_k_scale_kernel(const double* __restrict__ V, const double* __restrict__ ev,
+                                   const int* __restrict__ order, int n, int k, double* __restrict__ Pk,
+                                   int32_t* info) {
+    const double s1 = ev[order[0]], sk = ev[order[k - 1]];
+    const bool ok = (sk > 0.0) && (sk > 1e-12 * fmax(s1, 0.0));
+    if (blockIdx.x == 0 && threadIdx.x == 0) *info = ok ? 0 : 1;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int r = e / k, j = e % k;
+    const int src = order[j];
+    Pk[e] = ok ? V[(size_t)r * n + src] / sqrt(ev[src]) : 0.0;
+}
+
+// Pw[:, j] = V[:, order[j]] / ev[order[j]];  evals_out[j] = ev[order[j]]
+__global__ void whiten_scale_kernel(const double* __restrict__ V, const double* __restrict__ ev,
+                                    const int* __restrict__ order, int k, const int32_t* info,
+                                    double* __restrict__ Pw, double* __restrict__ evals_out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * k) return;
+    const int r = e / k, j = e % k;
+    const int src = order[j];
+    const double v = ev[src];
+    Pw[e] = (*info == 0 && v > 0.0) ? V[(size_t)r * k + src] / v : 0.0;
+    if (r == 0) evals_out[j] = v;
+}
+
+// per column: (max |W[r][j]|, first row reaching it) over a block of rows
+constexpr int kSignBlocks = 128;
+__global__ void colmax_partial_kernel(const double* __restrict__ W, int d, int k, double* __restrict__ pval,
+                                      int* __restrict__ pidx) {
+    const int per = (d + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * per, r1 = min(d, r0 + per);
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double best = -1.0;
+        int bi = r0;
+        for (int r = r0; r < r1; ++r) {
+            const double v = fabs(W[(size_t)r * k + j]);
+            if (v > best) { best = v; bi = r; }
+        }
+        pval[(size_t)blockIdx.x * k + j] = best;
+        pidx[(size_t)blockIdx.x * k + j] = bi;
+    }
+}
+
+__global__ void colsign_kernel(const double* __restrict__ W, const double* __restrict__ pval,
+                               const int* __restrict__ pidx, int nparts, int k, double* __restrict__ sign) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    double best = -1.0;
+    int bi = 0;
+    for (int b = 0; b < nparts; ++b) {
+        const double v = pval[(size_t)b * k + j];
+        if (v > best) { best = v; bi = pidx[(size_t)b * k + j]; }
+    }
+    sign[j] = (W[(size_t)bi * k + j] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ void apply_sign_kernel(double* __restrict__ W, const double* __restrict__ sign, int d, int k,
+                                  void* __restrict__ W_lo, int lo_dtype) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)d * k) return;
+    const double v = W[e] * sign[e % k];
+    W[e] = v;
+    if (W_lo) {
+        if (lo_dtype == OTM_F32) static_cast<float*>(W_lo)[e] = static_cast<float>(v);
+        else static_cast<__bf16*>(W_lo)[e] = f32_to_bf16(static_cast<float>(v));
+    }
+}
+
+// Pq[:, j] = V[:, j] / sqrt(ev[j]) for the orthonormal basis Y (Y^T Y)^(-1/2);
+// info = 1 if an eigenvalue of the Gram is not positive enough (rank deficient)
+__global__ void orth_scale_kernel(const double* __restrict__ V, const double* __restrict__ ev, int m,
+                                  double* __restrict__ Pq, int32_t* info) {
+    double emax = 0.0;
+    for (int j = 0; j < m; ++j) emax = fmax(emax, ev[j]);
+    bool ok = emax > 0.0;
+    for (int j = 0; j < m; ++j) ok = ok && (ev[j] > 1e-14 * emax);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) *info = ok ? 0 : 1;
+    if (e >= m * m) return;
+    const int j = e % m;
+    Pq[e] = ok ? V[e] / sqrt(ev[j]) : 0.0;
+}
+
+// ------------------------------------------------------------- unwhitening
+// lambda_i = kappa ||phi_i||^3, UL[a][i] = lambda_i u_i[a], alpha_hat
+__global__ void factor_stats_kernel(const float* __restrict__ Phi, int k, double kappa, double* __restrict__ lam,
+                                    double* __restrict__ UL, double* __restrict__ alpha_hat) {
+    __shared__ double s_inv2[kMaxK];
+    __shared__ double s_total;
+    const int i = threadIdx.x;
+    if (i < k) {
+        double nn = 0.0;
+        for (int a = 0; a < k; ++a) {
+            const double v = Phi[(size_t)i * k + a];
+            nn += v * v;
+        }
+        const double nrm = sqrt(nn);
+        const double l = kappa * nrm * nn;
+        lam[i] = l;
+        for (int a = 0; a < k; ++a) UL[(size_t)a * k + i] = l * Phi[(size_t)i * k + a] / nrm;
+        s_inv2[i] = 1.0 / (l * l);
+    }
+    __syncthreads();
+    if (i == 0) {
+        double t = 0.0;
+        for (int j = 0; j < k; ++j) t += s_inv2[j];
+        s_total = t;
+    }
+    __syncthreads();
+    if (i < k && alpha_hat) alpha_hat[i] = s_inv2[i] / s_total;
+}
+
+// Ginv = V diag(1/ev) V^T (k x k); info = 1 if an eigenvalue is not positive
+__global__ void spd_inverse_kernel(const double* __restrict__ V, const double* __restrict__ ev, int k,
+                                   double* __restrict__ Ginv, int32_t* info) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = true;
+    double emax = 0.0;
+    for (int m = 0; m < k; ++m) emax = fmax(emax, ev[m]);
+    for (int m = 0; m < k; ++m) ok = ok && (ev[m] > 1e-300) && (ev[m] > 1e-14 * emax);
+    if (e == 0) *info = ok ? 0 : 1;
+    if (e >= k * k) return;
+    const int r = e / k, c = e % k;
+    double s = 0.0;
+    for (int m = 0; m < k; ++m) s += V[(size_t)r * k + m] * V[(size_t)c * k + m] / ev[m];
+    Ginv[e] = ok ? s : 0.0;
+}
+
+// per-block column sums of max(mu, 0), clipping mu in place
+__global__ void clip_colsum_partial_kernel(double* __restrict__ mu, int d, int k, double* __restrict__ part) {
+    const int per = (d + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * per, r1 = min(d, r0 + per);
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double s = 0.0;
+        for (int r = r0; r < r1; ++r) {
+            double v = mu[(size_t)r * k + j];
+            if (v < 0.0) { v = 0.0; mu[(size_t)r * k + j] = 0.0; }
+            s += v;
+        }
+        part[(size_t)blockIdx.x * k + j] = s;
+    }
+}
+
+__global__ void col_normalize_kernel(double* __restrict__ mu, const double* __restrict__ colsum, int d, int k) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)d * k) return;
+    const double s = colsum[e % k];
+    mu[e] = (s > 0.0) ? mu[e] / s : 0.0;
+}
+
+constexpr int kColBlocks = 128;
+
+}  // namespace
+}  // namespace otm
+
+using namespace otm;
+
+extern "C" size_t otm_whitener_workspace(int32_t d, int32_t k_tilde, int32_t k) {
+    if (d < 1 || k_tilde < 1 || k < 1) return 0;
+    const size_t kt = k_tilde;
+    size_t b = 0;
+    b += ws_round(sizeof(double) * kt * kt) * 2;                      // Omega, V
+    b += ws_round(sizeof(double) * kt) + ws_round(sizeof(int) * kt);  // ev, order
+    b += ws_round(sizeof(double) * kt * k);                           // Pk
+    b += ws_round(sizeof(double) * (size_t)d * k);                    // B
+    b += ws_round(sizeof(double) * (size_t)k * k) * 3;                // Gram, V_B, Pw
+    b += ws_round(sizeof(double) * k) + ws_round(sizeof(int) * k);    // ev_B, order_B
+    size_t part = gemm_tn_ws(d, k_tilde, k_tilde);
+    const size_t p2 = gemm_tn_ws(d, k, k);
+    if (p2 > part) part = p2;
+    b += part;
+    b += ws_round(sizeof(double) * kSignBlocks * k) + ws_round(sizeof(int) * kSignBlocks * k);
+    b += ws_round(sizeof(double) * k);                                // signs
+    return b;
+}
+
+extern "C" int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, int32_t k, double* W,
+                            double* evals, void* W_lo, int w_lo_dtype, int32_t* info, void* ws, size_t ws_bytes,
+                            otm_stream stream) {
+    OTM_REQUIRE(O && S && W && evals && info, OTM_EINVAL, "O, S, W, evals, info must not be NULL");
+    OTM_REQUIRE(d >= 1 && k >= 1 && k <= k_tilde && k_tilde <= kJacMaxN && k <= d, OTM_ESHAPE,
+                "need 1 <= k <= k_tilde <= 256 and k <= d");
+    OTM_REQUIRE(W_lo == nullptr || w_lo_dtype == OTM_F32 || w_lo_dtype == OTM_BF16, OTM_EDTYPE,
+                "W_lo must be F32 or BF16");
+    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whitener_workspace(d, k_tilde, k), OTM_EWORKSPACE,
+                "whitener workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    const int kt = k_tilde;
+    double* Om = wc.take<double>((size_t)kt * kt);
+    double* Vo = wc.take<double>((size_t)kt * kt);
+    double* ev = wc.take<double>(kt);
+    int* ord = wc.take<int>(kt);
+    double* Pk = wc.take<double>((size_t)kt * k);
+    double* Bm = wc.take<double>((size_t)d * k);
+    double* Gr = wc.take<double>((size_t)k * k);
+    double* Vb = wc.take<double>((size_t)k * k);
+    double* Pw = wc.take<double>((size_t)k * k);
+    double* evb = wc.take<double>(k);
+    int* ordb = wc.take<int>(k);
+    size_t part_bytes = gemm_tn_ws(d, kt, kt);
+    if (gemm_tn_ws(d, k, k) > part_bytes) part_bytes = gemm_tn_ws(d, k, k);
+    double* part = wc.take<double>(part_bytes / sizeof(double));
+    double* pval = wc.take<double>((size_t)kSignBlocks * k);
+    int* pidx = wc.take<int>((size_t)kSignBlocks * k);
+    double* sgn = wc.take<double>(k);
+    int st;
+    if ((st = gemm_tn(S, kt, O, kt, d, kt, kt, Om, part, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((kt * kt + 255) / 256), dim3(256), 0, s, Om, kt);
+    if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
+    if ((st = jacobi(Om, Vo, kt, ev, ord, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(top_k_scale_kernel, dim3((kt * k + 255) / 256), dim3(256), 0, s, Vo, ev, ord, kt, k, Pk, info);
+    if ((st = check_launch("top_k_scale_kernel")) != OTM_OK) return st;
+    if ((st = gemm_nn(O, kt, Pk, k, Bm, k, d, kt, k, s)) != OTM_OK) return st;
+    if ((st = gemm_tn(Bm, k, Bm, k, d, k, k, Gr, part, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Gr, k);
+    if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
+    if ((st = jacobi(Gr, Vb, k, evb, ordb, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(whiten_scale_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Vb, evb, ordb, k, info, Pw,
+                       evals);
+    if ((st = check_launch("whiten_scale_kernel")) != OTM_OK) return st;
+    if ((st = gemm_nn(Bm, k, Pw, k, W, k, d, k, k, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(colmax_partial_kernel, dim3(kSignBlocks), dim3(128), 0, s, W, d, k, pval, pidx);
+    if ((st = check_launch("colmax_partial_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(colsign_kernel, dim3((k + 127) / 128), dim3(128), 0, s, W, pval, pidx, kSignBlocks, k, sgn);
+    if ((st = check_launch("colsign_kernel")) != OTM_OK) return st;
+    const int64_t total = (int64_t)d * k;
+    hipLaunchKernelGGL(apply_sign_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, sgn, d, k, W_lo,
+                       w_lo_dtype);
+    return check_launch("apply_sign_kernel");
+}
+
+extern "C" size_t otm_orthonormalize_workspace(int32_t d, int32_t m) {
+    if (d < 1 || m < 1) return 0;
+    size_t b = ws_round(sizeof(double) * (size_t)m * m) * 3;   // Gram, V, Pq
+    b += ws_round(sizeof(double) * m) + ws_round(sizeof(int) * m);
+    b += gemm_tn_ws(d, m, m);
+    return b;
+}
+
+extern "C" int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double* Q, int32_t* info, void* ws,
+                                  size_t ws_bytes, otm_stream stream) {
+    OTM_REQUIRE(Y && Q && info, OTM_EINVAL, "Y, Q, info must not be NULL");
+    OTM_REQUIRE(d >= 1 && m >= 1 && m <= d && m <= kJacMaxN, OTM_ESHAPE, "need 1 <= m <= min(d, 256)");
+    OTM_REQUIRE(Y != Q, OTM_EINVAL, "Y and Q must not alias");
+    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_orthonormalize_workspace(d, m), OTM_EWORKSPACE,
+                "orthonormalize workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    double* Gr = wc.take<double>((size_t)m * m);
+    double* V = wc.take<double>((size_t)m * m);
+    double* Pq = wc.take<double>((size_t)m * m);
+    double* ev = wc.take<double>(m);
+    int* ord = wc.take<int>(m);
+    double* part = wc.take<double>(gemm_tn_ws(d, m, m) / sizeof(double));
+    int st;
+    if ((st = gemm_tn(Y, m, Y, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, Gr, m);
+    if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
+    if ((st = jacobi(Gr, V, m, ev, ord, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(orth_scale_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, V, ev, m, Pq, info);
+    if ((st = check_launch("orth_scale_kernel")) != OTM_OK) return st;
+    return gemm_nn(Y, m, Pq, m, Q, m, d, m, m, s);
+}
+
+extern "C" size_t otm_unwhiten_workspace(int32_t d, int32_t k) {
+    if (d < 1 || k < 1) return 0;
+    size_t b = 0;
+    b += ws_round(sizeof(double) * (size_t)k * k) * 5;   // UL, Gram, V, Ginv, Z
+    b += ws_round(sizeof(double) * k) + ws_round(sizeof(int) * k);
+    b += gemm_tn_ws(d, k, k);
+    b += ws_round(sizeof(double) * (size_t)kColBlocks * k);
+    b += ws_round(sizeof(double) * k);
+    return b;
+}
+
+extern "C" int otm_unwhiten_topics(const double* W, int32_t d, int32_t k, const float* Phi, double theta, double* mu,
+                                   double* alpha_hat, double* lambda, int32_t* info, void* ws, size_t ws_bytes,
+                                   otm_stream stream) {
+    OTM_REQUIRE(W && Phi && mu && alpha_hat && lambda && info, OTM_EINVAL, "null pointer argument");
+    OTM_REQUIRE(d >= 1 && k >= 1 && k <= kMaxK && k <= d, OTM_ESHAPE, "need 1 <= k <= min(d, 128)");
+    OTM_REQUIRE(std::isfinite(theta), OTM_EINVAL, "theta must be finite");
+    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_unwhiten_workspace(d, k), OTM_EWORKSPACE,
+                "unwhiten workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    double* UL = wc.take<double>((size_t)k * k);
+    double* Gr = wc.take<double>((size_t)k * k);
+    double* V = wc.take<double>((size_t)k * k);
+    double* Gi = wc.take<double>((size_t)k * k);
+    double* Z = wc.take<double>((size_t)k * k);
+    double* ev = wc.take<double>(k);
+    int* ord = wc.take<int>(k);
+    double* part = wc.take<double>(gemm_tn_ws(d, k, k) / sizeof(double));
+    double* cpart = wc.take<double>((size_t)kColBlocks * k);
+    double* csum = wc.take<double>(k);
+    int st;
+    hipLaunchKernelGGL(factor_stats_kernel, dim3(1), dim3(kMaxK), 0, s, Phi, k, 0.5 * (1.0 + theta), lambda, UL,
+                       alpha_hat);
+    if ((st = check_launch("factor_stats_kernel")) != OTM_OK) return st;
+    if ((st = gemm_tn(W, k, W, k, d, k, k, Gr, part, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Gr, k);
+    if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
+    if ((st = jacobi(Gr, V, k, ev, ord, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(spd_inverse_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, V, ev, k, Gi, info);
+    if ((st = check_launch("spd_inverse_kernel")) != OTM_OK) return st;
+    if ((st = gemm_nn(Gi, k, UL, k, Z, k, k, k, k, s)) != OTM_OK) return st;
+    if ((st = gemm_nn(W, k, Z, k, mu, k, d, k, k, s)) != OTM_OK) return st;
+    hipLaunchKernelGGL(clip_colsum_partial_kernel, dim3(kColBlocks), dim3(128), 0, s, mu, d, k, cpart);
+    if ((st = check_launch("clip_colsum_partial_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((k + 255) / 256), dim3(256), 0, s, cpart, kColBlocks, (int64_t)k, csum);
+    if ((st = check_launch("reduce_parts_kernel")) != OTM_OK) return st;
+    const int64_t total = (int64_t)d * k;
+    hipLaunchKernelGGL(col_normalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, mu, csum, d, k);
+    return check_launch("col_normalize_kernel");
+}

@@ -1,0 +1,449 @@
+// Sparse products of the hot path.
+//
+//  * whitening SpMM (Section 3.1 whitened data, Appendix A):
+//      Y[t, :] = r_t sum_j C[t, j] W[j, :]
+//    A group of LPR lanes owns one row; lane l of the group owns VPL
+//    consecutive columns of W and Y, so every stored entry of the row costs one
+//    coalesced gather of the W row (LPR*VPL*sizeof(W) bytes).  Column indices
+//    and values are loaded LPR at a time, one per lane, and broadcast within the
+//    group by shuffles; four W rows are in flight per iteration.  The group's
+//    FP32 accumulators also feed per-block column sums (fixed order) for ybar.
+//
+//  * FP64 passes of the second-moment operator (Section 2, Eq. 2moment;
+//    Section 4.2): T1 = diag(w2) C S, then C^T T1 together with C^T w2 and
+//    C^T w1, then M1^T S and the rank-one / diagonal epilogue.
+//
+// Malformed CSR cannot make these kernels read out of bounds: row ranges are
+// clamped to [0, nnz] and entries with a column outside [0, n_cols) are skipped.
+#include <cmath>
+
+#include "otm_internal.h"
+
+namespace otm {
+namespace {
+
+constexpr int kSpmmThreads = 256;
+constexpr int kSpmmMaxBlocks = 2048;
+
+template <class T>
+__device__ __forceinline__ float to_f(T x) { return static_cast<float>(x); }
+
+template <int VPL, class TW>
+struct WVec;
+template <> struct WVec<1, float> { using T = float; };
+template <> struct WVec<2, float> { using T = float __attribute__((ext_vector_type(2))); };
+template <> struct WVec<4, float> { using T = float __attribute__((ext_vector_type(4))); };
+template <> struct WVec<1, __bf16> { using T = __bf16; };
+template <> struct WVec<2, __bf16> { using T = bf16x2; };
+template <> struct WVec<4, __bf16> { using T = bf16x4; };
+template <> struct WVec<8, __bf16> { using T = bf16x8; };
+
+template <int VPL, class TW>
+__device__ __forceinline__ void load_w(const TW* p, float (&out)[VPL]) {
+    using V = typename WVec<VPL, TW>::T;
+    const V v = *reinterpret_cast<const V*>(p);
+    if constexpr (VPL == 1) {
+        out[0] = to_f(v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VPL; ++e) out[e] = to_f(v[e]);
+    }
+}
+
+__device__ __forceinline__ void clamp_row(const int32_t* rowptr, int64_t nnz, int row, int64_t& b, int64_t& e) {
+    b = rowptr[row];
+    e = rowptr[row + 1];
+    b = b < 0 ? 0 : (b > nnz ? nnz : b);
+    e = e < b ? b : (e > nnz ? nnz : e);
+}
+
+// Y = diag(r) C W ; per-block column sums of the FP32 rows into part[blockIdx][0..k)
+template <int VPL, class TW, class TY>
+__global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int normalize, const TW* __restrict__ W,
+                                                              int k, TY* __restrict__ Y, int ldy, int lpr,
+                                                              float* __restrict__ part) {
+    extern __shared__ float s_colsum[];   // [rows_per_block][lpr*VPL]
+    const int tid = threadIdx.x;
+    const int g_lane = tid % lpr;          // lane within the row group
+    const int slot = tid / lpr;
+    const int rows_per_block = kSpmmThreads / lpr;
+    const int col0 = g_lane * VPL;
+    const bool active = col0 < k;
+    float colacc[VPL];
+#pragma unroll
+    for (int e = 0; e < VPL; ++e) colacc[e] = 0.f;
+
+    const int n_rows = C.n_rows;
+    const int64_t nnz = C.nnz;
+    for (int rb = blockIdx.x; rb * rows_per_block < n_rows; rb += gridDim.x) {
+        const int row = rb * rows_per_block + slot;
+        if (row < n_rows) {
+            int64_t b, e;
+            clamp_row(C.rowptr, nnz, row, b, e);
+            float acc[VPL];
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) acc[v] = 0.f;
+            float rowsum = 0.f;
+            for (int64_t base = b; base < e; base += lpr) {
+                const int64_t my = base + g_lane;
+                int32_t my_col = -1;
+                float my_val = 0.f;
+                if (my < e) {
+                    my_col = C.colidx[my];
+                    my_val = C.vals ? C.vals[my] : 1.0f;
+                    if (my_col < 0 || my_col >= C.n_cols) { my_col = -1; my_val = 0.f; }
+                }
+                const int cnt = static_cast<int>(min<int64_t>(lpr, e - base));
+                int jj = 0;
+                for (; jj + 4 <= cnt; jj += 4) {
+                    int c4[4];
+                    float v4[4];
+                    float w4[4][VPL];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        c4[u] = __shfl(my_col, jj + u, lpr);
+                        v4[u] = __shfl(my_val, jj + u, lpr);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (active && c4[u] >= 0) load_w<VPL>(W + (size_t)c4[u] * k + col0, w4[u]);
+                        else {
+#pragma unroll
+                            for (int v = 0; v < VPL; ++v) w4[u][v] = 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        rowsum += v4[u];
+#pragma unroll
+                        for (int v = 0; v < VPL; ++v) acc[v] += v4[u] * w4[u][v];
+                    }
+                }
+                for (; jj < cnt; ++jj) {
+                    const int c = __shfl(my_col, jj, lpr);
+                    const float val = __shfl(my_val, jj, lpr);
+                    float w1[VPL];
+                    if (active && c >= 0) load_w<VPL>(W + (size_t)c * k + col0, w1);
+                    else {
+#pragma unroll
+                        for (int v = 0; v < VPL; ++v) w1[v] = 0.f;
+                    }
+                    rowsum += val;
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) acc[v] += val * w1[v];
+                }
+            }
+            const float r = normalize ? (rowsum > 0.f ? 1.0f / rowsum : 0.f) : 1.0f;
+            TY* yrow = Y + (size_t)row * ldy;
+            if (active) {
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) {
+                    const float y = acc[v] * r;
+                    colacc[v] += y;
+                    yrow[col0 + v] = static_cast<TY>(y);
+                }
+            }
+            for (int c = k + g_lane; c < ldy; c += lpr) yrow[c] = static_cast<TY>(0.0f);
+        }
+    }
+    // block column sums in a fixed order: slots 0..rows_per_block-1
+    const int width = lpr * VPL;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) s_colsum[slot * width + col0 + v] = colacc[v];
+    __syncthreads();
+    for (int c = tid; c < k; c += kSpmmThreads) {
+        float s = 0.f;
+        for (int sl = 0; sl < rows_per_block; ++sl) s += s_colsum[sl * width + c];
+        part[(size_t)blockIdx.x * k + c] = s;
+    }
+}
+
+// out[c] = scale * sum_b part[b][c], fixed order, FP64 accumulation
+__global__ void colsum_finalize_kernel(const float* __restrict__ part, int nblocks, int k, double scale,
+                                       float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * k + c];
+    out[c] = static_cast<float>(s * scale);
+}
+
+template <int VPL, class TW, class TY>
+int launch_whiten(const otm_csr& C, int normalize, const void* W, int k, void* Y, int ldy, float* part,
+                  int nblocks, int lpr, hipStream_t st) {
+    const size_t shm = sizeof(float) * (kSpmmThreads / lpr) * lpr * VPL;
+    hipLaunchKernelGGL((whiten_kernel<VPL, TW, TY>), dim3(nblocks), dim3(kSpmmThreads), shm, st, C, normalize,
+                       static_cast<const TW*>(W), k, static_cast<TY*>(Y), ldy, lpr, part);
+    return check_launch("whiten_kernel");
+}
+
+template <class TW, class TY>
+int dispatch_whiten(int vpl, const otm_csr& C, int normalize, const void* W, int k, void* Y, int ldy, float* part,
+                    int nblocks, int lpr, hipStream_t st) {
+    switch (vpl) {
+        case 1: return launch_whiten<1, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+        case 2: return launch_whiten<2, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+        case 4: return launch_whiten<4, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+        default:
+            if constexpr (sizeof(TW) == 2) return launch_whiten<8, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+            return fail(OTM_EINVAL, "bad vector width");
+    }
+}
+
+struct WhitenPlan {
+    int vpl, lpr, nblocks;
+};
+
+WhitenPlan plan_whiten(int32_t n_rows, int k, int w_dtype) {
+    WhitenPlan p{};
+    const int vmax = (w_dtype == OTM_BF16) ? 8 : 4;
+    p.vpl = 1;
+    for (int v = vmax; v > 1; v >>= 1)
+        if (k % v == 0) { p.vpl = v; break; }
+    const int lanes = (k + p.vpl - 1) / p.vpl;
+    p.lpr = 1;
+    while (p.lpr < lanes) p.lpr <<= 1;
+    if (p.lpr < 2) p.lpr = 2;
+    const int rpb = kSpmmThreads / (p.lpr > 64 ? 64 : p.lpr);
+    int64_t blocks = (n_rows + rpb - 1) / rpb;
+    if (blocks > kSpmmMaxBlocks) blocks = kSpmmMaxBlocks;
+    if (blocks < 1) blocks = 1;
+    p.nblocks = static_cast<int>(blocks);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 passes of the M2 operator.  One wave per row, lane owns up to 4 of the
+// m <= 256 columns (lane, lane+64, ...).
+// ---------------------------------------------------------------------------
+constexpr int kM2Threads = 256;
+
+// T1[t,:] = w2_t sum_j C[t,j] S[j,:]; w1[t], w2[t] from the row sum when normalize
+__global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int normalize, const double* __restrict__ S,
+                                                              int m, double* __restrict__ T1, double* __restrict__ w1,
+                                                              double* __restrict__ w2, int32_t* info) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kM2Threads + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * kM2Threads) >> 6;
+    for (int row = wave; row < C.n_rows; row += nwaves) {
+        int64_t b, e;
+        clamp_row(C.rowptr, C.nnz, row, b, e);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double rs = 0.0;
+        for (int64_t p = b; p < e; ++p) {
+            const int32_t c = C.colidx[p];
+            if (c < 0 || c >= C.n_cols) continue;
+            const double v = C.vals ? static_cast<double>(C.vals[p]) : 1.0;
+            rs += v;
+            const double* srow = S + (size_t)c * m;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int col = lane + 64 * u;
+                if (col < m) acc[u] += v * srow[col];
+            }
+        }
+        double a1 = 1.0, a2 = 1.0;
+        if (normalize) {
+            if (rs < 2.0) {
+                if (lane == 0) *info = 1;
+                a1 = 0.0;
+                a2 = 0.0;
+            } else {
+                a1 = 1.0 / rs;
+                a2 = 1.0 / (rs * (rs - 1.0));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int col = lane + 64 * u;
+            if (col < m) T1[(size_t)row * m + col] = a2 * acc[u];
+        }
+        if (lane == 0) {
+            w1[row] = a1;
+            w2[row] = a2;
+        }
+    }
+}
+
+// O[a,:] = sum_x CT[a,x] T1[x,:];  u[a] = sum_x CT[a,x] w2[x];  M1[a] = (1/n) sum_x CT[a,x] w1[x]
+__global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const double* __restrict__ T1, int m,
+                                                              const double* __restrict__ w1, const double* __restrict__ w2,
+                                                              double inv_n, double* __restrict__ O, double* __restrict__ u,
+                                                              double* __restrict__ M1) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kM2Threads + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * kM2Threads) >> 6;
+    for (int row = wave; row < CT.n_rows; row += nwaves) {
+        int64_t b, e;
+        clamp_row(CT.rowptr, CT.nnz, row, b, e);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double su = 0.0, sm = 0.0;
+        for (int64_t p = b; p < e; ++p) {
+            const int32_t x = CT.colidx[p];
+            if (x < 0 || x >= CT.n_cols) continue;
+            const double v = CT.vals ? static_cast<double>(CT.vals[p]) : 1.0;
+            su += v * w2[x];
+            sm += v * w1[x];
+            const double* trow = T1 + (size_t)x * m;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = lane + 64 * q;
+                if (col < m) acc[q] += v * trow[col];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int col = lane + 64 * q;
+            if (col < m) O[(size_t)row * m + col] = acc[q];
+        }
+        if (lane == 0) {
+            u[row] = su;
+            M1[row] = sm * inv_n;
+        }
+    }
+}
+
+// part[b][c] = sum over this block's rows r of w[r] X[r][c]   (fixed order)
+constexpr int kWcsThreads = 256;
+constexpr int kWcsBlocks = 256;
+__global__ __launch_bounds__(kWcsThreads) void weighted_colsum_partial_kernel(const double* __restrict__ w,
+                                                                              const double* __restrict__ X, int rows,
+                                                                              int m, double* __restrict__ part) {
+    const int per = (rows + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * per;
+    const int r1 = min(rows, r0 + per);
+    for (int c = threadIdx.x; c < m; c += kWcsThreads) {
+        double s = 0.0;
+        for (int r = r0; r < r1; ++r) s += w[r] * X[(size_t)r * m + c];
+        part[(size_t)blockIdx.x * m + c] = s;
+    }
+}
+
+__global__ void sum_partials64_kernel(const double* __restrict__ part, int nparts, int m, double* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[(size_t)b * m + c];
+    out[c] = s;
+}
+
+// O = (alpha0+1)/n (O - u * S) - alpha0 M1 v^T
+__global__ void m2_epilogue_kernel(double* __restrict__ O, const double* __restrict__ S, const double* __restrict__ u,
+                                   const double* __restrict__ M1, const double* __restrict__ v, int d, int m,
+                                   double scale, double alpha0) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)d * m) return;
+    const int a = static_cast<int>(idx / m), c = static_cast<int>(idx % m);
+    O[idx] = scale * (O[idx] - u[a] * S[idx]) - alpha0 * M1[a] * v[c];
+}
+
+}  // namespace
+}  // namespace otm
+
+using namespace otm;
+
+extern "C" size_t otm_whiten_workspace(int32_t n_rows, int32_t k) {
+    if (n_rows < 0 || k < 1) return 0;
+    const WhitenPlan p = plan_whiten(n_rows, k, OTM_BF16);
+    const WhitenPlan q = plan_whiten(n_rows, k, OTM_F32);
+    const int nb = p.nblocks > q.nblocks ? p.nblocks : q.nblocks;
+    return ws_round(sizeof(float) * (size_t)nb * k);
+}
+
+extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, void* Y,
+                          int y_dtype, int32_t ldy, float* ybar, void* ws, size_t ws_bytes, otm_stream stream) {
+    int st = validate_csr_header(C, "C");
+    if (st != OTM_OK) return st;
+    OTM_REQUIRE(W != nullptr && (Y != nullptr || C->n_rows == 0), OTM_EINVAL, "W and Y must not be NULL");
+    OTM_REQUIRE(k >= 1 && ldy >= k, OTM_ESHAPE, "need k >= 1 and ldy >= k");
+    OTM_REQUIRE(w_dtype == OTM_F32 || w_dtype == OTM_BF16, OTM_EDTYPE, "W must be F32 or BF16");
+    OTM_REQUIRE(y_dtype == OTM_F32 || y_dtype == OTM_BF16, OTM_EDTYPE, "Y must be F32 or BF16");
+    OTM_REQUIRE(y_dtype != OTM_BF16 || ldy % 8 == 0, OTM_ESHAPE, "BF16 Y needs ldy % 8 == 0");
+    OTM_REQUIRE(y_dtype != OTM_F32 || ldy % 4 == 0, OTM_ESHAPE, "F32 Y needs ldy % 4 == 0");
+    const WhitenPlan p = plan_whiten(C->n_rows, k, w_dtype);
+    OTM_REQUIRE(p.lpr <= 64, OTM_ECAPACITY, "k too large for the whitening kernel (k <= 64 * vector width)");
+    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whiten_workspace(C->n_rows, k), OTM_EWORKSPACE,
+                "whiten workspace too small");
+    if (C->n_rows == 0) {
+        if (ybar) {
+            hipError_t e = hipMemsetAsync(ybar, 0, sizeof(float) * k, as_stream(stream));
+            if (e != hipSuccess) return hip_fail(e, "whiten ybar clear");
+        }
+        return OTM_OK;
+    }
+    hipStream_t s = as_stream(stream);
+    float* part = static_cast<float*>(ws);
+    if (w_dtype == OTM_F32) {
+        st = (y_dtype == OTM_F32) ? dispatch_whiten<float, float>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s)
+                                  : dispatch_whiten<float, __bf16>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s);
+    } else {
+        st = (y_dtype == OTM_F32) ? dispatch_whiten<__bf16, float>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s)
+                                  : dispatch_whiten<__bf16, __bf16>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s);
+    }
+    if (st != OTM_OK) return st;
+    if (ybar) {
+        hipLaunchKernelGGL(colsum_finalize_kernel, dim3((k + 127) / 128), dim3(128), 0, s, part, p.nblocks, k,
+                           1.0 / C->n_rows, ybar);
+        return check_launch("colsum_finalize_kernel");
+    }
+    return OTM_OK;
+}
+
+extern "C" size_t otm_m2_apply_workspace(int32_t n, int32_t d, int32_t k_tilde) {
+    if (n < 0 || d < 0 || k_tilde < 1) return 0;
+    size_t b = 0;
+    b += ws_round(sizeof(double) * (size_t)n * k_tilde);  // T1
+    b += 2 * ws_round(sizeof(double) * (size_t)n);        // w1, w2
+    b += 2 * ws_round(sizeof(double) * (size_t)d);        // u, M1
+    b += ws_round(sizeof(double) * (size_t)kWcsBlocks * k_tilde);
+    b += ws_round(sizeof(double) * (size_t)k_tilde);      // v
+    return b;
+}
+
+extern "C" int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, double alpha0, const double* S,
+                            int32_t k_tilde, double* O, int32_t* info, void* ws, size_t ws_bytes, otm_stream stream) {
+    int st = validate_csr_header(C, "C");
+    if (st != OTM_OK) return st;
+    st = validate_csr_header(CT, "CT");
+    if (st != OTM_OK) return st;
+    OTM_REQUIRE(S != nullptr && O != nullptr && info != nullptr, OTM_EINVAL, "S, O, info must not be NULL");
+    OTM_REQUIRE(CT->n_rows == C->n_cols && CT->n_cols == C->n_rows && CT->nnz == C->nnz, OTM_ESHAPE,
+                "CT must be the transpose of C");
+    OTM_REQUIRE(k_tilde >= 1 && k_tilde <= 256, OTM_ECAPACITY, "need 1 <= k_tilde <= 256");
+    OTM_REQUIRE(C->n_rows >= 1, OTM_ESHAPE, "need at least one sample");
+    OTM_REQUIRE(std::isfinite(alpha0) && alpha0 >= 0.0, OTM_EINVAL, "alpha0 must be finite and >= 0");
+    const int n = C->n_rows, d = C->n_cols;
+    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_m2_apply_workspace(n, d, k_tilde), OTM_EWORKSPACE,
+                "m2_apply workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    double* T1 = wc.take<double>((size_t)n * k_tilde);
+    double* w1 = wc.take<double>(n);
+    double* w2 = wc.take<double>(n);
+    double* u = wc.take<double>(d);
+    double* M1 = wc.take<double>(d);
+    double* part = wc.take<double>((size_t)kWcsBlocks * k_tilde);
+    double* v = wc.take<double>(k_tilde);
+    hipError_t e = hipMemsetAsync(info, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_fail(e, "m2_apply info clear");
+    const int waves_per_block = kM2Threads / 64;
+    auto blocks_for = [&](int rows) {
+        int64_t b = (rows + waves_per_block - 1) / waves_per_block;
+        return static_cast<int>(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    };
+    hipLaunchKernelGGL(m2_pass1_kernel, dim3(blocks_for(n)), dim3(kM2Threads), 0, s, *C, normalize, S, k_tilde, T1, w1,
+                       w2, info);
+    if ((st = check_launch("m2_pass1_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(m2_pass2_kernel, dim3(blocks_for(d)), dim3(kM2Threads), 0, s, *CT, T1, k_tilde, w1, w2,
+                       1.0 / n, O, u, M1);
+    if ((st = check_launch("m2_pass2_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(weighted_colsum_partial_kernel, dim3(kWcsBlocks), dim3(kWcsThreads), 0, s, M1, S, d, k_tilde,
+                       part);
+    if ((st = check_launch("weighted_colsum_partial_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(sum_partials64_kernel, dim3((k_tilde + 255) / 256), dim3(256), 0, s, part, kWcsBlocks, k_tilde, v);
+    if ((st = check_launch("sum_partials64_kernel")) != OTM_OK) return st;
+    const int64_t total = (int64_t)d * k_tilde;
+    hipLaunchKernelGGL(m2_epilogue_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, O, S, u, M1, v, d,
+                       k_tilde, (alpha0 + 1.0) / n, alpha0);
+    return check_launch("m2_epilogue_kernel");
+}

@@ -1,0 +1,313 @@
+"""Thin Python binding of libotm (ctypes).  Argument marshalling only: every
+step runs in the library's HIP kernels.  torch provides device memory and the
+current stream; nothing here computes the method.
+
+The library must be built (``paper_1309_0787_amd.build.build()``); without it
+every call raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotm.so")
+
+F64, F32, BF16 = 0, 1, 2
+_TORCH_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+_DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_dbl = ctypes.c_double
+
+
+class OtmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"otm error {status}: {msg}")
+        self.status = status
+
+
+class OtmNotPSD(OtmError):
+    pass
+
+
+class OtmNonFinite(OtmError):
+    pass
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n_rows", _i32), ("n_cols", _i32), ("nnz", _i64),
+                ("rowptr", _vp), ("colidx", _vp), ("vals", _vp)]
+
+
+class _SgdParams(ctypes.Structure):
+    _fields_ = [("k", _i32), ("batch", _i32), ("passes", _i32), ("ldy", _i32), ("y_dtype", _i32),
+                ("compensated", _i32), ("alpha0", _dbl), ("theta", _dbl), ("beta0", _dbl),
+                ("beta_tau", _dbl)]
+
+
+_SIGS = {
+    "otm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "otm_last_error": (ctypes.c_char_p, []),
+    "otm_version": (ctypes.c_int, []),
+    "otm_max_k": (ctypes.c_int, []),
+    "otm_max_batch": (ctypes.c_int, []),
+    "otm_csr_check_workspace": (_sz, []),
+    "otm_csr_check": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_i64), _vp, _sz, _vp]),
+    "otm_m2_apply_workspace": (_sz, [_i32, _i32, _i32]),
+    "otm_m2_apply": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), ctypes.c_int, _dbl, _vp, _i32,
+                                    _vp, _vp, _vp, _sz, _vp]),
+    "otm_whitener_workspace": (_sz, [_i32, _i32, _i32]),
+    "otm_whitener": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "otm_orthonormalize_workspace": (_sz, [_i32, _i32]),
+    "otm_orthonormalize": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "otm_whiten_workspace": (_sz, [_i32, _i32]),
+    "otm_whiten": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _vp, ctypes.c_int,
+                                  _i32, _vp, _vp, _sz, _vp]),
+    "otm_sgd_step": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "otm_sgd_run": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i64,
+                                   _i64, _vp, _vp, _vp, _vp, _vp]),
+    "otm_unwhiten_workspace": (_sz, [_i32, _i32]),
+    "otm_unwhiten_topics": (ctypes.c_int, [_vp, _i32, _i32, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_recover_pi_workspace": (_sz, [_i32]),
+    "otm_recover_pi": (ctypes.c_int, [_vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _dbl, _vp, _vp, _sz, _vp]),
+    "otm_tensor_form": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _vp, _vp]),
+    "otm_residual_workspace": (_sz, [_i32, _i32]),
+    "otm_residual": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libotm.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OtmError(-6, f"{LIB_PATH} not found: build the HIP library first "
+                               "(paper_1309_0787_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().otm_last_error().decode()
+        raise OtmError(status, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise OtmError(-1, "tensor must live on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ CSR
+class DeviceCSR:
+    """A CSR whose arrays live on the GPU (int32 rowptr/colidx, float32 vals or None)."""
+
+    def __init__(self, n_rows, n_cols, rowptr, colidx, vals=None):
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+        self.rowptr, self.colidx, self.vals = rowptr, colidx, vals
+        self.nnz = int(colidx.numel())
+
+    @staticmethod
+    def from_host(csr, device) -> "DeviceCSR":
+        rp = torch.from_numpy(csr.rowptr).to(device=device, dtype=torch.int32)
+        ci = torch.from_numpy(csr.colidx).to(device=device, dtype=torch.int32)
+        v = None if csr.vals is None else torch.from_numpy(csr.vals).to(device=device, dtype=torch.float32)
+        return DeviceCSR(csr.n_rows, csr.n_cols, rp, ci, v)
+
+    def c(self) -> _CSR:
+        return _CSR(self.n_rows, self.n_cols, self.nnz, _ptr(self.rowptr), _ptr(self.colidx), _ptr(self.vals))
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+
+def csr_check(C: DeviceCSR, stream=None) -> int:
+    ws = _ws(lib().otm_csr_check_workspace(), C.device)
+    bad = _i64(0)
+    cc = C.c()
+    _check(lib().otm_csr_check(ctypes.byref(cc), ctypes.byref(bad), _ptr(ws), ws.numel(), _stream(stream)))
+    return int(bad.value)
+
+
+# ------------------------------------------------------------------ a1, a2
+def m2_apply(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: torch.Tensor, stream=None):
+    """O = M2 S (FP64).  Raises OtmError if a document has fewer than 2 tokens."""
+    d, kt = S.shape
+    O = torch.empty((d, kt), dtype=torch.float64, device=S.device)
+    info = torch.zeros(1, dtype=torch.int32, device=S.device)
+    ws = _ws(lib().otm_m2_apply_workspace(C.n_rows, C.n_cols, kt), S.device)
+    c1, c2 = C.c(), CT.c()
+    _check(lib().otm_m2_apply(ctypes.byref(c1), ctypes.byref(c2), int(normalize), float(alpha0), _ptr(S), kt,
+                              _ptr(O), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
+    if int(info.item()) != 0:
+        raise OtmError(-1, "a document has fewer than 2 tokens")
+    return O
+
+
+def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = F32, stream=None):
+    """(W FP64 d x k, evals FP64 k, W_lo in w_lo_dtype or None).  Raises OtmNotPSD."""
+    d, kt = O.shape
+    W = torch.empty((d, k), dtype=torch.float64, device=O.device)
+    ev = torch.empty(k, dtype=torch.float64, device=O.device)
+    W_lo = None if w_lo_dtype is None else torch.empty((d, k), dtype=_TORCH_DTYPE[w_lo_dtype], device=O.device)
+    info = torch.zeros(1, dtype=torch.int32, device=O.device)
+    ws = _ws(lib().otm_whitener_workspace(d, kt, k), O.device)
+    _check(lib().otm_whitener(_ptr(O), _ptr(S), d, kt, k, _ptr(W), _ptr(ev), _ptr(W_lo),
+                              F32 if w_lo_dtype is None else w_lo_dtype, _ptr(info), _ptr(ws), ws.numel(),
+                              _stream(stream)))
+    if int(info.item()) != 0:
+        raise OtmNotPSD(-4, "projected second moment has no k positive eigenvalues")
+    return W, ev, W_lo
+
+
+def orthonormalize(Y: torch.Tensor, stream=None) -> torch.Tensor:
+    """Q = Y (Y^T Y)^(-1/2) (FP64)."""
+    d, m = Y.shape
+    Q = torch.empty_like(Y)
+    info = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    ws = _ws(lib().otm_orthonormalize_workspace(d, m), Y.device)
+    _check(lib().otm_orthonormalize(_ptr(Y), d, m, _ptr(Q), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
+    if int(info.item()) != 0:
+        raise OtmError(-4, "sketch is rank deficient")
+    return Q
+
+
+def power_sketch(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: torch.Tensor, q: int,
+                 stream=None):
+    """Sketch for the whitener: Q_0 = S, Q_j = orth(M2 Q_{j-1}); returns
+    (Q_q, O = M2 Q_q).  q = 0 returns (S, M2 S)."""
+    Q = S
+    for _ in range(q):
+        Q = orthonormalize(m2_apply(C, CT, normalize, alpha0, Q, stream), stream)
+    return Q, m2_apply(C, CT, normalize, alpha0, Q, stream)
+
+
+# ------------------------------------------------------------------ a3
+def default_ldy(k: int) -> int:
+    return (k + 7) // 8 * 8
+
+
+def whiten(C: DeviceCSR, normalize: bool, W: torch.Tensor, y_dtype: int = F32, ldy: int | None = None,
+           want_ybar: bool = True, out: torch.Tensor | None = None, stream=None):
+    """Y (n x ldy, y_dtype) and ybar (k FP32, or None)."""
+    d, k = W.shape
+    ldy = default_ldy(k) if ldy is None else ldy
+    Y = out if out is not None else torch.empty((C.n_rows, ldy), dtype=_TORCH_DTYPE[y_dtype], device=W.device)
+    ybar = torch.empty(k, dtype=torch.float32, device=W.device) if want_ybar else None
+    ws = _ws(lib().otm_whiten_workspace(C.n_rows, k), W.device)
+    cc = C.c()
+    _check(lib().otm_whiten(ctypes.byref(cc), int(normalize), _ptr(W), _DTYPE_CODE[W.dtype], k, _ptr(Y), y_dtype,
+                            ldy, _ptr(ybar), _ptr(ws), ws.numel(), _stream(stream)))
+    return Y, ybar
+
+
+# ------------------------------------------------------------------ a4, a5
+@dataclass
+class SgdParams:
+    k: int
+    batch: int = 100
+    passes: int = 1
+    ldy: int = 0
+    y_dtype: int = F32
+    compensated: bool = True
+    alpha0: float = 0.0
+    theta: float = 1.0
+    beta0: float = 0.01
+    beta_tau: float = 1e12
+
+    def c(self) -> _SgdParams:
+        ldy = self.ldy if self.ldy else default_ldy(self.k)
+        return _SgdParams(self.k, self.batch, self.passes, ldy, self.y_dtype, int(self.compensated), self.alpha0,
+                          self.theta, self.beta0, self.beta_tau)
+
+
+def sgd_step(p: SgdParams, rows: int, YA, YB, YC, ybar3: torch.Tensor, beta: float, Phi: torch.Tensor,
+             Phi_comp: torch.Tensor | None = None, stream=None):
+    """One STGD step on the first `rows` rows; Phi (k x k FP32, row i = phi_i) updated in place."""
+    cp = p.c()
+    _check(lib().otm_sgd_step(ctypes.byref(cp), rows, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), float(beta),
+                              _ptr(Phi), _ptr(Phi_comp), _stream(stream)))
+    return Phi
+
+
+def sgd_run(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, perms: torch.Tensor | None, Phi: torch.Tensor,
+            restarts: int = 1, perm_stride: int = 0, start_step: int = 0, end_step: int = -1,
+            Phi_comp: torch.Tensor | None = None, snapshots: torch.Tensor | None = None,
+            nonfinite: torch.Tensor | None = None, stream=None):
+    """Runs STGD steps [start_step, end_step) for `restarts` independent runs
+    (Phi: restarts x k x k FP32, updated in place)."""
+    cp = p.c()
+    _check(lib().otm_sgd_run(ctypes.byref(cp), n, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), _ptr(perms),
+                             perm_stride, restarts, start_step, end_step, _ptr(Phi), _ptr(Phi_comp),
+                             _ptr(snapshots), _ptr(nonfinite), _stream(stream)))
+    return Phi
+
+
+# ------------------------------------------------------------------ a6
+def unwhiten_topics(W: torch.Tensor, Phi: torch.Tensor, theta: float = 1.0, stream=None):
+    d, k = W.shape
+    mu = torch.empty((d, k), dtype=torch.float64, device=W.device)
+    ah = torch.empty(k, dtype=torch.float64, device=W.device)
+    lam = torch.empty(k, dtype=torch.float64, device=W.device)
+    info = torch.zeros(1, dtype=torch.int32, device=W.device)
+    ws = _ws(lib().otm_unwhiten_workspace(d, k), W.device)
+    _check(lib().otm_unwhiten_topics(_ptr(W), d, k, _ptr(Phi), float(theta), _ptr(mu), _ptr(ah), _ptr(lam),
+                                     _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
+    if int(info.item()) != 0:
+        raise OtmError(-4, "W^T W is not positive definite")
+    return mu, ah, lam
+
+
+def recover_pi(Y: torch.Tensor, k: int, Phi: torch.Tensor, theta: float = 1.0, tau: float = 0.0, stream=None):
+    n, ldy = Y.shape
+    Pi = torch.empty((k, n), dtype=torch.float32, device=Y.device)
+    ws = _ws(lib().otm_recover_pi_workspace(k), Y.device)
+    _check(lib().otm_recover_pi(_ptr(Y), _DTYPE_CODE[Y.dtype], ldy, n, k, _ptr(Phi), float(theta), float(tau),
+                                _ptr(Pi), _ptr(ws), ws.numel(), _stream(stream)))
+    return Pi
+
+
+# ------------------------------------------------------------------ loss
+def tensor_form(YA, YB, YC, k: int, ybar3: torch.Tensor, alpha0: float, stream=None):
+    n, ldy = YA.shape
+    T = torch.empty((k, k, k), dtype=torch.float64, device=YA.device)
+    _check(lib().otm_tensor_form(_ptr(YA), _ptr(YB), _ptr(YC), _DTYPE_CODE[YA.dtype], ldy, n, k, _ptr(ybar3),
+                                 float(alpha0), _ptr(T), _stream(stream)))
+    return T
+
+
+def residual(T: torch.Tensor, Phis: torch.Tensor, stream=None):
+    k = T.shape[0]
+    Phis = Phis.reshape(-1, k, k)
+    cnt = Phis.shape[0]
+    R = torch.empty(cnt, dtype=torch.float64, device=T.device)
+    ws = _ws(lib().otm_residual_workspace(k, cnt), T.device)
+    _check(lib().otm_residual(_ptr(T), k, _ptr(Phis), cnt, _ptr(R), _ptr(ws), ws.numel(), _stream(stream)))
+    return R

@@ -1,0 +1,100 @@
+"""GPU parity of the whitening SpMM (Section 3.1 whitened data) against the
+FP64 oracle, on the same rounded W.
+
+Bars: FP32 Y within 2e-6 relative per row (FP32 accumulation of <= a few
+hundred terms); BF16 Y within 2^-8 relative per entry of the row scale plus
+the FP32 bar; ybar within 1e-6 relative (FP64 reduction of FP32 rows)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import bf16_round, csr_dev, dev, f32_round, host, to_dev
+
+from paper_1309_0787_amd import otm
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_rows(Yg, Yref, k, tol_rel):
+    Yg = Yg[:, :k]
+    scale = np.maximum(np.abs(Yref).max(axis=1, keepdims=True), 1e-30)
+    err = np.abs(Yg - Yref) / scale
+    assert err.max() <= tol_rel, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+@pytest.mark.parametrize("k", [3, 10, 16, 50, 100, 128])
+@pytest.mark.parametrize("w_dt,y_dt", [(otm.F32, otm.F32), (otm.BF16, otm.BF16), (otm.BF16, otm.F32),
+                                       (otm.F32, otm.BF16)])
+def test_whiten_graph_rows(k, w_dt, y_dt):
+    g = synth.mmsb(n=1300, k=4, alpha0=0.3, p=0.2, q=0.02, n_x=700, seed=k)
+    W = synth.projection(g.C.n_cols, k, seed=3)
+    Wr = bf16_round(W) if w_dt == otm.BF16 else f32_round(W)
+    Wd = to_dev(Wr, torch.bfloat16 if w_dt == otm.BF16 else torch.float32)
+    Y, ybar = otm.whiten(csr_dev(g.C), False, Wd, y_dtype=y_dt)
+    torch.cuda.synchronize()
+    Yref, ybref = oracle.whiten(g.C, Wr, normalize=False)
+    Yg = host(Y)
+    tol = 2e-6 if y_dt == otm.F32 else 2.0 ** -8
+    _check_rows(Yg, Yref, k, tol)
+    assert np.all(Yg[:, k:] == 0.0)
+    np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
+
+
+@pytest.mark.parametrize("k", [7, 50, 64])
+def test_whiten_document_views_normalised(k):
+    inst = synth.lda(d=3000, k=5, alpha0=1.0, beta=0.1, n_docs=2051, mean_len=40.0, seed=k)
+    W = f32_round(synth.projection(3000, k, seed=5))
+    for v in inst.views:
+        Y, ybar = otm.whiten(csr_dev(v), True, to_dev(W), y_dtype=otm.F32)
+        torch.cuda.synchronize()
+        Yref, ybref = oracle.whiten(v, W, normalize=True)
+        _check_rows(host(Y), Yref, k, 2e-6)
+        np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
+
+
+def test_whiten_empty_rows_and_empty_matrix():
+    # rows 0, 3 and the last are empty
+    rowptr = np.array([0, 0, 2, 3, 3, 5, 5], dtype=np.int32)
+    colidx = np.array([1, 4, 0, 2, 3], dtype=np.int32)
+    C = synth.CSR(6, 5, rowptr, colidx, np.array([1, 2, 3, 4, 5], dtype=np.float32))
+    W = f32_round(synth.projection(5, 6, seed=1))
+    for norm in (False, True):
+        Y, ybar = otm.whiten(csr_dev(C), norm, to_dev(W), y_dtype=otm.F32)
+        torch.cuda.synchronize()
+        Yref, ybref = oracle.whiten(C, W, normalize=False)
+        if norm:
+            rs = np.asarray(C.to_scipy().sum(1)).ravel()
+            Yref = np.where(rs[:, None] > 0, Yref / np.where(rs > 0, rs, 1)[:, None], 0.0)
+            ybref = Yref.mean(0)
+        np.testing.assert_allclose(host(Y)[:, :6], Yref, atol=1e-6)
+        np.testing.assert_allclose(host(ybar), ybref, atol=1e-6)
+    E = synth.CSR(0, 5, np.zeros(1, dtype=np.int32), np.zeros(0, dtype=np.int32), None)
+    Y, ybar = otm.whiten(csr_dev(E), False, to_dev(W), y_dtype=otm.F32)
+    torch.cuda.synchronize()
+    assert Y.shape[0] == 0 and np.all(host(ybar) == 0)
+
+
+def test_whiten_skips_out_of_range_columns_and_check_reports_them():
+    rowptr = np.array([0, 2, 4], dtype=np.int32)
+    colidx = np.array([0, 9, -3, 1], dtype=np.int32)     # 9 and -3 are outside [0, 3)
+    C = synth.CSR(2, 3, rowptr, colidx, None)
+    W = f32_round(synth.projection(3, 4, seed=2))
+    Cd = csr_dev(C)
+    assert otm.csr_check(Cd) == 2
+    Y, _ = otm.whiten(Cd, False, to_dev(W), y_dtype=otm.F32)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(host(Y)[:, :4], np.stack([W[0], W[1]]), atol=1e-7)
+    good = csr_dev(synth.mmsb(n=100, k=2, alpha0=0.3, p=0.3, q=0.1, seed=1).C)
+    assert otm.csr_check(good) == 0
+
+
+def test_whiten_rejects_bad_arguments():
+    C = csr_dev(synth.CSR(2, 3, np.array([0, 1, 2], dtype=np.int32), np.array([0, 1], dtype=np.int32), None))
+    W = to_dev(np.ones((3, 4)))
+    with pytest.raises(otm.OtmError) as e:
+        otm.whiten(C, False, W, y_dtype=otm.BF16, ldy=4)           # BF16 needs ldy % 8 == 0
+    assert e.value.status == -2
+    with pytest.raises(otm.OtmError):
+        otm.whiten(C, False, to_dev(np.ones((3, 4)), torch.float64), y_dtype=otm.F32)   # FP64 W
