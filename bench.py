@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload: mixed-membership graph, n = 100000 nodes (X/A = 50000/50000),
+k = 100 communities, alpha0 = 0.5, p = 0.05, q = 0.001, seeded synthetic.
+One step = the whole path on one batch of input already resident in HBM:
+power-iterated M2 sketch (FP64) -> randomized whitener (FP64) -> whitening
+SpMM (BF16 W and Y, FP32 accumulation) -> STGD run (50 passes, mini-batch 100,
+BF16 matrix-core contractions, FP32 compensated update) -> memberships (FP64).
+
+value = whitened samples pushed through STGD per second of a whole step
+(n_X * passes / step time).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="mmsb_large", n=100000, n_x=50000, k=100, alpha0=0.5, p=0.05, q=0.001, batch=100, passes=50,
+                q_power=3, beta0=1e-3, beta_tau=2500.0, tau_pi=0.1)
+PEAK_BF16 = 2.5e15          # dense MFMA bf16, FLOP/s
+PEAK_HBM = 8.0e12           # bytes/s
+# HBM counters of the STGD kernel (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), per launch,
+# valid only for the kernel source they were taken on.
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sgd_kernel_mmsb_large_counters.json")
+
+
+def sgd_flops(n: int, batch: int, k: int, passes: int) -> float:
+    """Algorithmic flops of one STGD run: per step 2 PA/PB products (2*2*B*k^2),
+    YC^T Q (2*B*k^2), Phi^T Phi and Phi (G*G) (2*2*k^3)."""
+    full, rem = divmod(n, batch)
+    per_pass = full * (6.0 * batch * k * k + 4.0 * k ** 3)
+    if rem:
+        per_pass += 6.0 * rem * k * k + 4.0 * k ** 3
+    return per_pass * passes
+
+
+def kernel_hash() -> str:
+    src = open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", "stgd.hip"), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def counters_traffic():
+    try:
+        c = json.load(open(COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return c.get("bytes_per_launch")
+
+
+def cpu_baseline(inst, w):
+    """The FP64 oracle on the same workload (whole path, one decomposition)."""
+    import numpy as np
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count()
+    k = w["k"]
+    S = synth.projection(inst.C.n_cols, 2 * k, seed=1)
+    perms = synth.permutations(inst.C.n_rows, w["passes"], seed=2)
+    Phi0 = synth.initial_factors(k, seed=4)
+    t0 = time.perf_counter()
+    Q, O = oracle.power_sketch(inst.C, S, w["alpha0"], False, w["q_power"])
+    W, _ = oracle.whitener_rsvd(O, Q, k)
+    Y, ybar = oracle.whiten(inst.C, W, False)
+    yb = np.stack([ybar] * 3)
+    Phi = oracle.sgd_run(Y, Y, Y, yb, Phi0, perms, w["batch"], w["beta0"], w["beta_tau"], w["alpha0"])
+    oracle.recover_pi(Y, Phi, w["tau_pi"])
+    el = time.perf_counter() - t0
+    return {"value": inst.C.n_rows * w["passes"] / el, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"whole path once on the same graph (FP64): sketch q={w['q_power']}, whitener, whitening, "
+                      f"{w['passes']} STGD passes, memberships; {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quality", action="store_true", help="also report the residual of the final factors")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path is single-GPU here",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1309_0787_amd import otm
+    if not os.path.exists(otm.LIB_PATH):
+        from paper_1309_0787_amd import build
+        build.build()
+    from paper_1309_0787_amd import pipeline
+    import synth
+
+    w = WORKLOAD
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    inst = synth.mmsb(w["n"], w["k"], w["alpha0"], w["p"], w["q"], w["n_x"], seed=synth.BASE_SEED)
+    t_gen = time.perf_counter() - t_gen
+    k, n = w["k"], inst.C.n_rows
+    C = otm.DeviceCSR.from_host(inst.C, dev)
+    CT = otm.DeviceCSR.from_host(inst.CT, dev)
+    S = torch.as_tensor(synth.projection(inst.C.n_cols, 2 * k, seed=1), device=dev)
+    perms = torch.as_tensor(synth.permutations(n, w["passes"], seed=2), device=dev)
+    Phi_init = torch.as_tensor(synth.initial_factors(k, seed=4).T.copy(), dtype=torch.float32, device=dev)[None]
+    Phi = torch.empty_like(Phi_init)
+    cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=otm.BF16,
+                             batch=w["batch"], passes=w["passes"], beta0=w["beta0"], beta_tau=w["beta_tau"],
+                             tau_pi=w["tau_pi"])
+
+    def step(timer=None):
+        Phi.copy_(Phi_init)
+        return pipeline.fit([C], C, CT, S, Phi, perms, cfg, pi_view=0, timer=timer)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    timers = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tm = pipeline.Timer(True)
+        res = step(tm)
+        timers.append(tm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el * 1e3 / args.steps
+    stages = {}
+    for tm in timers:
+        for kname, v in tm.spans_ms().items():
+            stages[kname] = stages.get(kname, 0.0) + v / args.steps
+    sgd_ms = stages["stgd"]
+    flops = sgd_flops(n, w["batch"], k, w["passes"])
+    achieved = flops / (sgd_ms * 1e-3)
+    out = {
+        "metric": "whitened samples/sec through tensor SGD at k=100",
+        "value": n * w["passes"] / (ms_per_step * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"MMSB n={w['n']} (X/A {w['n_x']}/{w['n'] - w['n_x']}) k={k} alpha0={w['alpha0']} "
+                               f"p={w['p']} q={w['q']} nnz(G[X,A])={inst.C.nnz}",
+                   "batch": w["batch"], "passes": w["passes"], "restarts": 1, "sketch_power_iterations": w["q_power"],
+                   "precision": "BF16 W/Y and STGD contractions, FP32 accumulate and master, FP64 sketch/whitener/post"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16, "traffic": counters_traffic(),
+                     "kernel": "sgd_kernel<MmaBF16,128>", "flops_per_launch": flops, "launch_ms": sgd_ms},
+        "stage_ms": {kname: round(v, 4) for kname, v in stages.items()},
+        "sgd_samples_per_s": n * w["passes"] / (sgd_ms * 1e-3),
+        "sgd_us_per_step": sgd_ms * 1e3 / (w["passes"] * ((n + w["batch"] - 1) // w["batch"])),
+        "generation_s": round(t_gen, 2),
+    }
+    if args.quality:
+        T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
+        out["quality"] = {"residual": float(otm.residual(T, res.Phi[0]).item()),
+                          "nonfinite": int(res.nonfinite.item())}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -251,7 +251,7 @@ def sgd_run(YA, YB, YC, ybar, Phi0, perms, batch: int, beta0: float, tau: float,
 # ----------------------------------------------------------------------------
 # Loss (for measurement only: the hot path never forms the tensor)
 # ----------------------------------------------------------------------------
-def whitened_tensor(YA, YB, YC, ybar, alpha0: float, chunk: int = 4096) -> np.ndarray:
+def whitened_tensor(YA, YB, YC, ybar, alpha0: float, chunk: int = 1024) -> np.ndarray:
     """The whitened tensor T (k x k x k) of Section 3.2, formed explicitly:
       T = a/n sum_t yA_t x yB_t x yC_t
           - b/n sum_t [yA_t x yB_t x ybarC + yA_t x ybarB x yC_t + ybarA x yB_t x yC_t]
@@ -262,7 +262,9 @@ def whitened_tensor(YA, YB, YC, ybar, alpha0: float, chunk: int = 4096) -> np.nd
     T = np.zeros((k, k, k))
     for s in range(0, n, chunk):
         A, Bv, Cv = YA[s:s + chunk], YB[s:s + chunk], YC[s:s + chunk]
-        T += a / n * np.einsum("ti,tj,tl->ijl", A, Bv, Cv)
+        # sum_t yA_t x yB_t x yC_t as (rows of yA kron yB)^T yC, one matmul
+        kron = (A[:, :, None] * Bv[:, None, :]).reshape(A.shape[0], k * k)
+        T += a / n * (kron.T @ Cv).reshape(k, k, k)
         T -= b / n * np.einsum("ij,l->ijl", A.T @ Bv, ybC)
         T -= b / n * np.einsum("il,j->ijl", A.T @ Cv, ybB)
         T -= b / n * np.einsum("jl,i->ijl", Bv.T @ Cv, ybA)

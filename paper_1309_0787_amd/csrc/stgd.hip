@@ -16,8 +16,16 @@
 // product, so the update of a Phi tile needs only the O and D tiles the same
 // wave computed.  LDS holds operand copies of Phi (phi_i-major, plus an
 // a-major copy for BF16 fragments), a buffer that carries G*G and then Q from
-// the accumulator layout to the operand layout, for BF16 the batch of YC
-// (a-major, the operand layout of YC^T Q), and small vectors.
+// the accumulator layout to the operand layout, the mini-batch of whitened
+// rows, and small vectors.
+//
+// Batch staging (NSTAGE = 1 for one shared view, 3 for three views): the rows
+// of step t+1 are fetched into registers while step t computes (indices during
+// the Phi^T Phi and Phi (G*G) products, data during the rest) and written to
+// LDS row-major at the start of step t+1, so the products never wait on
+// global memory.  NSTAGE = 0 (shapes whose batch does not fit in LDS) reads
+// the rows from global memory inside the products.
+//
 // Four workgroup barriers per step: after G*G, after O (the buffer then
 // takes Q), after Q, after the update.
 #include <cmath>
@@ -36,59 +44,78 @@ struct MmaF32 {
     using Y = float;
     using Op = float;
     using Frag = float;
+    using Chunk = f32x4;                      // 16-byte row piece of the batch
     static constexpr int KI = 4;
     static constexpr int EPL = 1;
-    static constexpr int KMUL = 16;   // padding multiple of k and of the batch
-    static constexpr int SPAD = 4;    // LDS row padding (elements)
+    static constexpr int KMUL = 16;           // padding multiple of k and of the batch
+    static constexpr int SPAD = 4;            // LDS row padding (elements)
+    static constexpr int CH = 4;              // elements per chunk
     static constexpr bool kPhiT = false;
-    static constexpr bool kStageC = false;   // YC operand read straight from global memory
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     __device__ static Frag lds(const Op* p) { return *p; }
     __device__ static Op to_op(float x) { return x; }
     __device__ static float op_to_f(Op x) { return x; }
-    __device__ static float y_to_f(Y x) { return x; }
+    __device__ static Frag zero_frag() { return 0.0f; }
     // fragment of EPL consecutive row elements a0.. (masked at k)
     __device__ static Frag yrow(const Y* row, int a0, int k) {
         return (row != nullptr && a0 < k) ? row[a0] : 0.0f;
     }
-    __device__ static void store4(Op* p, f32x4 v) {
-        *reinterpret_cast<f32x4*>(p) = v;
+    __device__ static Chunk load_chunk(const Y* p, int valid) {
+        Chunk v = *reinterpret_cast<const Chunk*>(p);
+#pragma unroll
+        for (int e = 0; e < CH; ++e)
+            if (e >= valid) v[e] = 0.0f;
+        return v;
     }
+    __device__ static Chunk zero_chunk() { return Chunk{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static void store4(Op* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
+    __device__ static f32x4 load4(const Op* p) { return *reinterpret_cast<const f32x4*>(p); }
 };
 
 struct MmaBF16 {
     using Y = __bf16;
     using Op = __bf16;
     using Frag = bf16x8;
+    using Chunk = bf16x8;
     static constexpr int KI = 32;
     static constexpr int EPL = 8;
     static constexpr int KMUL = 32;
     static constexpr int SPAD = 8;
+    static constexpr int CH = 8;
     static constexpr bool kPhiT = true;
-    static constexpr bool kStageC = true;    // YC batch staged in LDS, a-major
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
     __device__ static Frag lds(const Op* p) { return *reinterpret_cast<const bf16x8*>(p); }
     __device__ static Op to_op(float x) { return f32_to_bf16(x); }
     __device__ static float op_to_f(Op x) { return bf16_to_f32(x); }
-    __device__ static float y_to_f(Y x) { return bf16_to_f32(x); }
-    __device__ static Frag yrow(const Y* row, int a0, int k) {
+    __device__ static Frag zero_frag() {
         bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = f32_to_bf16(0.0f);
+        return v;
+    }
+    __device__ static Frag yrow(const Y* row, int a0, int k) {
         if (row != nullptr && a0 < k) {
             // ldy % 8 == 0 and a0 % 8 == 0: the 16-byte load stays inside the row
-            v = *reinterpret_cast<const bf16x8*>(row + a0);
+            bf16x8 v = *reinterpret_cast<const bf16x8*>(row + a0);
 #pragma unroll
             for (int e = 0; e < 8; ++e)
                 if (a0 + e >= k) v[e] = f32_to_bf16(0.0f);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = f32_to_bf16(0.0f);
+            return v;
         }
+        return zero_frag();
+    }
+    __device__ static Chunk load_chunk(const Y* p, int valid) {
+        Chunk v = *reinterpret_cast<const Chunk*>(p);
+#pragma unroll
+        for (int e = 0; e < CH; ++e)
+            if (e >= valid) v[e] = f32_to_bf16(0.0f);
         return v;
     }
+    __device__ static Chunk zero_chunk() { return zero_frag(); }
     __device__ static void store4(Op* p, f32x4 v) {
         bf16x4 o;
         o[0] = f32_to_bf16(v[0]);
@@ -120,46 +147,81 @@ constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTR = 2;  // tile rows per wave (4 wave rows x 2 = 8 tiles = 128)
 
-template <class M, int KPMAX>
+template <class M, int KP, int NSTAGE>
+struct SgdSmem {
+    using Op = typename M::Op;
+    using Y = typename M::Y;
+    static constexpr int SP = KP + M::SPAD;        // Phi rows
+    static constexpr int SB = kMaxBatch + M::SPAD;    // exchange buffer rows (t or j)
+    static constexpr int SY = KP + M::SPAD;        // staged batch rows
+    static constexpr bool kStageCT = (NSTAGE == 0) && M::kPhiT;   // BF16 fallback: YC batch a-major
+    alignas(16) Op phi[KP * SP];
+    alignas(16) Op phiT[M::kPhiT ? KP * SP : 1];
+    alignas(16) Op buf[KP * SB];
+    alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * kMaxBatch * SY : 1];
+    alignas(16) Op yct[kStageCT ? KP * SB : 1];
+    alignas(16) int32_t idx[kMaxBatch];
+    alignas(16) float ybar[3 * KP];
+    alignas(16) float m[2 * KP];
+    alignas(16) float s[4 * KP];
+};
+
+template <class M, int KP, int NSTAGE>
+constexpr size_t smem_bytes() { return sizeof(SgdSmem<M, KP, NSTAGE>); }
+
+struct StepInfo {
+    int64_t pass;
+    int s, row0, nb;
+};
+
+__device__ __forceinline__ StepInfo step_info(const SgdArgs& g, int64_t t) {
+    StepInfo si;
+    si.pass = t / g.spp;
+    si.s = static_cast<int>(t - si.pass * g.spp);
+    si.row0 = si.s * g.batch;
+    si.nb = min(g.batch, g.n - si.row0);
+    return si;
+}
+
+template <class M, int KP, int NSTAGE>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     using Op = typename M::Op;
     using Y = typename M::Y;
-    constexpr int TC = KPMAX / 32;                 // tile columns per wave
-    constexpr int SP = KPMAX + M::SPAD;            // stride of Phi rows in LDS
-    constexpr int SB = kMaxBatch + M::SPAD;        // stride of the exchange buffer rows
-    __shared__ __attribute__((aligned(16))) Op sPhi[KPMAX * SP];
-    __shared__ __attribute__((aligned(16))) Op sPhiT[M::kPhiT ? KPMAX * SP : 1];
-    __shared__ __attribute__((aligned(16))) Op sBuf[KPMAX * SB];
-    __shared__ __attribute__((aligned(16))) Op sYC[M::kStageC ? KPMAX * SB : 1];
-    __shared__ int32_t sIdx[kMaxBatch];
-    __shared__ float sYbar[3 * KPMAX];
-    __shared__ float sM[2 * KPMAX];
-    __shared__ float sS[4 * KPMAX];
+    using SM = SgdSmem<M, KP, NSTAGE>;
+    constexpr int NTK = KP / 16;
+    constexpr int TC = (NTK + 1) / 2;              // tile columns per wave
+    constexpr int TRK = (NTK + 3) / 4;             // tile rows per wave in the k x k products
+    constexpr int SP = SM::SP, SB = SM::SB, SY = SM::SY;
+    // batch chunks per thread (16 bytes each) when staging
+    constexpr int NCH = (kMaxBatch * KP / M::CH + kThreads - 1) / kThreads;
+    __shared__ __attribute__((aligned(16))) SM sm;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int wr = w >> 1, wc = w & 1;
+    // wave index in a scalar register: every tile guard below is a scalar branch
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = (w >> 1) & 3, wc = w & 1;
     const int l16 = lane & 15, q = lane >> 4;
 
     const int k = g.k;
-    const int KP = (k + M::KMUL - 1) / M::KMUL * M::KMUL;
     const int MB = (g.batch + M::KMUL - 1) / M::KMUL * M::KMUL;
-    const int NTK = KP / 16, NTM = MB / 16;
-    const int n = g.n, B = g.batch, ldy = g.ldy;
+    const int NTM = MB / 16;
+    const int n = g.n, ldy = g.ldy;
     const int r_id = blockIdx.x;
     float* Phi = g.Phi + (size_t)r_id * k * k;
     float* Comp = g.Phi_comp ? g.Phi_comp + (size_t)r_id * k * k : nullptr;
     float* Snap = g.snapshots ? g.snapshots + (size_t)r_id * g.passes * k * k : nullptr;
     const int32_t* perms = g.perms ? g.perms + (size_t)r_id * g.perm_stride : nullptr;
-    const Y* YA = static_cast<const Y*>(g.YA);
-    const Y* YB = static_cast<const Y*>(g.YB);
-    const Y* YC = static_cast<const Y*>(g.YC);
+    const Y* Yv[3] = {static_cast<const Y*>(g.YA), static_cast<const Y*>(g.YB), static_cast<const Y*>(g.YC)};
+    bool bad = false;
+    const float cmask = g.compensated ? 1.0f : 0.0f;
+    const float beta0f = static_cast<float>(g.beta0);
+    const float inv_tauf = static_cast<float>(1.0 / g.beta_tau);
 
     // ---- master copy of Phi in registers: tile (mt, nt) holds a = row, i = column
-    f32x4 phi[kTR][TC], comp[kTR][TC];
+    f32x4 phi[TRK][TC], comp[TRK][TC];
 #pragma unroll
-    for (int ti = 0; ti < kTR; ++ti)
+    for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
         for (int tj = 0; tj < TC; ++tj) {
             const int mt = wr + 4 * ti, nt = wc + 2 * tj;
@@ -174,112 +236,189 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                         if (Comp && g.compensated) cv[r] = Comp[(size_t)i * k + a];
                     }
                 }
-                M::store4(&sPhi[i * SP + mt * 16 + 4 * q], v);
+                M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                 if constexpr (M::kPhiT) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sPhiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
+                    for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
                 }
             }
             phi[ti][tj] = v;
             comp[ti][tj] = cv;
         }
-    for (int e = tid; e < 3 * KPMAX; e += kThreads) {
-        const int v = e / KPMAX, a = e % KPMAX;
-        sYbar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
+    for (int e = tid; e < 3 * KP; e += kThreads) {
+        const int v = e / KP, a = e % KP;
+        sm.ybar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
     }
+
+    // ---- batch prefetch state (NSTAGE > 0)
+    constexpr int cpr = KP / M::CH;                 // chunks per row
+    int32_t pidx[NCH];
+    typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
+    auto issue_index = [&](int64_t t) {
+        if constexpr (NSTAGE > 0) {
+            const bool live = t < g.end_step;
+            StepInfo si;
+            if (live) si = step_info(g, t);
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
+                const int tr = c / cpr;
+                int32_t r = -1;
+                if (live && c < MB * cpr && tr < si.nb) {
+                    r = perms ? perms[(size_t)si.pass * n + si.row0 + tr] : si.row0 + tr;
+                    if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
+                        r = 0;
+                        bad = true;
+                    }
+                }
+                pidx[j] = r;
+            }
+        }
+    };
+    auto issue_data = [&]() {
+        if constexpr (NSTAGE > 0) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
+                const int a0 = (c % cpr) * M::CH;
+#pragma unroll
+                for (int v = 0; v < NSTAGE; ++v)
+                    pbuf[v][j] = (pidx[j] >= 0 && a0 < k)
+                                     ? M::load_chunk(Yv[v] + (size_t)pidx[j] * ldy + a0, k - a0)
+                                     : M::zero_chunk();
+            }
+        }
+    };
+    auto commit = [&]() {
+        if constexpr (NSTAGE > 0) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
+                if (c < MB * cpr) {
+                    const int tr = c / cpr, a0 = (c % cpr) * M::CH;
+#pragma unroll
+                    for (int v = 0; v < NSTAGE; ++v)
+                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * kMaxBatch + tr) * SY + a0]) = pbuf[v][j];
+                }
+            }
+        }
+    };
+    issue_index(g.start_step);
+    issue_data();
     __syncthreads();
 
-    bool bad = false;
     for (int64_t t = g.start_step; t < g.end_step; ++t) {
-        const int64_t pass = t / g.spp;
-        const int s = static_cast<int>(t - pass * g.spp);
-        const int row0 = s * B;
-        const int nb = min(B, n - row0);
-        const float beta = static_cast<float>(g.beta0 / (1.0 + static_cast<double>(t) / g.beta_tau));
+        const StepInfo si = step_info(g, t);
+        const int nb = si.nb;
+        const float beta = beta0f / (1.0f + static_cast<float>(t) * inv_tauf);
 
         // ================= phase 1: batch rows, mA/mB, G = Phi^T Phi -> G*G
-        if (tid < nb) {
-            int32_t r = perms ? perms[(size_t)pass * n + row0 + tid] : row0 + tid;
-            if (r < 0 || r >= n) {   // a permutation entry out of range reads row 0 and is reported
-                r = 0;
-                bad = true;
+        commit();
+        issue_index(t + 1);
+        if constexpr (NSTAGE == 0) {
+            if (tid < nb) {
+                int32_t r = perms ? perms[(size_t)si.pass * n + si.row0 + tid] : si.row0 + tid;
+                if (r < 0 || r >= n) {
+                    r = 0;
+                    bad = true;
+                }
+                sm.idx[tid] = r;
             }
-            sIdx[tid] = r;
         }
         {
+            // mA, mB: thread (view v, column i, half h) sums half of a dot product
             const int v = tid >> 8, rem = tid & 255, i = rem >> 1, h = rem & 1;
             float acc = 0.f;
             if (i < KP) {
                 const int half = KP >> 1;
-                for (int a = h * half; a < (h + 1) * half; ++a)
-                    acc += M::op_to_f(sPhi[i * SP + a]) * sYbar[v * KPMAX + a];
+                const Op* prow = &sm.phi[i * SP + h * half];
+                const float* yb = &sm.ybar[v * KP + h * half];
+#pragma unroll 4
+                for (int a = 0; a < half; a += 8) {
+                    float x[8];
+                    if constexpr (M::EPL == 8) {
+                        const bf16x8 pv = *reinterpret_cast<const bf16x8*>(prow + a);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) x[e] = M::op_to_f(pv[e]);
+                    } else {
+                        const f32x4 p0 = M::load4(prow + a), p1 = M::load4(prow + a + 4);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) { x[e] = p0[e]; x[e + 4] = p1[e]; }
+                    }
+                    const f32x4 y0 = *reinterpret_cast<const f32x4*>(yb + a);
+                    const f32x4 y1 = *reinterpret_cast<const f32x4*>(yb + a + 4);
+                    acc += x[0] * y0[0] + x[1] * y0[1] + x[2] * y0[2] + x[3] * y0[3] +
+                           x[4] * y1[0] + x[5] * y1[1] + x[6] * y1[2] + x[7] * y1[3];
+                }
             }
             acc += __shfl_xor(acc, 1);
-            if (h == 0 && i < KP) sM[v * KPMAX + i] = acc;
+            if (h == 0 && i < KP) sm.m[v * KP + i] = acc;
         }
         {
-            f32x4 acc[kTR][TC];
+            f32x4 acc[TRK][TC];
 #pragma unroll
-            for (int ti = 0; ti < kTR; ++ti)
+            for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < KP; k0 += M::KI) {
-                typename M::Frag fa[kTR], fb[TC];
+            for (int k0 = 0; k0 < KP; k0 += M::KI) {
+                typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
-                for (int ti = 0; ti < kTR; ++ti) {
+                for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + 4 * ti;
-                    if (mt < NTK) fa[ti] = M::lds(&sPhi[(mt * 16 + l16) * SP + k0 + q * M::EPL]);
+                    fa[ti] = (mt < NTK) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
                 }
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + 2 * tj;
-                    if (nt < NTK) fb[tj] = M::lds(&sPhi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
+                    fb[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
                 }
 #pragma unroll
-                for (int ti = 0; ti < kTR; ++ti)
+                for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj)
                         if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
                             acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
             }
-            // G*G into the exchange buffer, column-major: sBuf[i*SB + j] = G[j][i]^2
+            // G*G into the exchange buffer, column-major: buf[i*SB + j] = G[j][i]^2
 #pragma unroll
-            for (int ti = 0; ti < kTR; ++ti)
+            for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int mt = wr + 4 * ti, nt = wc + 2 * tj;
                     if (mt < NTK && nt < NTK) {
                         f32x4 v = acc[ti][tj] * acc[ti][tj];
-                        M::store4(&sBuf[(nt * 16 + l16) * SB + mt * 16 + 4 * q], v);
+                        M::store4(&sm.buf[(nt * 16 + l16) * SB + mt * 16 + 4 * q], v);
                     }
                 }
         }
         __syncthreads();
 
         // ================= phase 2: O = Phi (G*G), kept in registers until the update
-        f32x4 oacc[kTR][TC];
+        f32x4 oacc[TRK][TC];
 #pragma unroll
-        for (int ti = 0; ti < kTR; ++ti)
+        for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) oacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < KP; k0 += M::KI) {
-            typename M::Frag fa[kTR], fb[TC];
+            typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
-            for (int ti = 0; ti < kTR; ++ti) {
+            for (int ti = 0; ti < TRK; ++ti) {
                 const int mt = wr + 4 * ti;
+                const int a = mt * 16 + l16;
                 if (mt < NTK) {
-                    const int a = mt * 16 + l16;
-                    if constexpr (M::kPhiT) fa[ti] = M::lds(&sPhiT[a * SP + k0 + q * M::EPL]);
-                    else fa[ti] = sPhi[(k0 + q) * SP + a];
+                    if constexpr (M::kPhiT) fa[ti] = M::lds(&sm.phiT[a * SP + k0 + q * M::EPL]);
+                    else fa[ti] = sm.phi[(k0 + q) * SP + a];
+                } else {
+                    fa[ti] = M::zero_frag();
                 }
             }
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + 2 * tj;
-                if (nt < NTK) fb[tj] = M::lds(&sBuf[(nt * 16 + l16) * SB + k0 + q * M::EPL]);
+                fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
             }
 #pragma unroll
-            for (int ti = 0; ti < kTR; ++ti)
+            for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj)
                     if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
@@ -287,8 +426,11 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
         }
         __syncthreads();   // every read of G*G is done: the buffer takes Q next
 
+        // rows of step t+1 start their trip from global memory now
+        issue_data();
+
         // ================= phase 3: PA, PB one tile row at a time -> Q into the
-        // exchange buffer (sBuf[i*SB + t] = Q[t][i]) and column sums of H
+        // exchange buffer (buf[i*SB + t] = Q[t][i]) and column sums of H
         {
             float colsum[TC];
 #pragma unroll
@@ -298,25 +440,38 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                 const int mt = wr + 4 * ti;
                 if (mt >= NTM) continue;
                 const int tr = mt * 16 + l16;
-                const bool ok = tr < nb;
-                const Y* rowA = ok ? YA + (size_t)sIdx[tr] * ldy : nullptr;
-                const Y* rowB = ok ? YB + (size_t)sIdx[tr] * ldy : nullptr;
+                const Y* rowA = nullptr;
+                const Y* rowB = nullptr;
+                if constexpr (NSTAGE == 0) {
+                    const bool ok = tr < nb;
+                    rowA = ok ? Yv[0] + (size_t)sm.idx[tr] * ldy : nullptr;
+                    rowB = ok ? Yv[1] + (size_t)sm.idx[tr] * ldy : nullptr;
+                }
+                const Y* sA = &sm.ybatch[tr * SY];
+                const Y* sB = &sm.ybatch[((NSTAGE == 3 ? 1 : 0) * kMaxBatch + tr) * SY];
                 f32x4 pa[TC], pb[TC];
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     pa[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                     pb[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-        for (int k0 = 0; k0 < KP; k0 += M::KI) {
-                    const typename M::Frag fa = M::yrow(rowA, k0 + q * M::EPL, k);
-                    const typename M::Frag fbv = M::yrow(rowB, k0 + q * M::EPL, k);
+                for (int k0 = 0; k0 < KP; k0 += M::KI) {
+                    typename M::Frag fa, fbv;
+                    if constexpr (NSTAGE == 0) {
+                        fa = M::yrow(rowA, k0 + q * M::EPL, k);
+                        fbv = M::yrow(rowB, k0 + q * M::EPL, k);
+                    } else {
+                        fa = M::lds(sA + k0 + q * M::EPL);
+                        fbv = (NSTAGE == 1) ? fa : M::lds(sB + k0 + q * M::EPL);
+                    }
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + 2 * tj;
                         if (nt < NTK) {
-                            const typename M::Frag fphi = M::lds(&sPhi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
+                            const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
                             pa[tj] = M::mma(fa, fphi, pa[tj]);
-                            pb[tj] = M::mma(fbv, fphi, pb[tj]);
+                            if (NSTAGE == 1) pb[tj] = pa[tj];
+                            else pb[tj] = M::mma(fbv, fphi, pb[tj]);
                         }
                     }
                 }
@@ -325,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     const int nt = wc + 2 * tj;
                     if (nt >= NTK) continue;
                     const int i = nt * 16 + l16;
-                    const float mA = sM[i], mB = sM[KPMAX + i];
+                    const float mA = sm.m[i], mB = sm.m[KP + i];
                     f32x4 qv;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -334,7 +489,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                         colsum[tj] += h;
                         qv[r] = g.a * h - g.b * xa * mB - g.b * mA * xb;
                     }
-                    M::store4(&sBuf[i * SB + mt * 16 + 4 * q], qv);
+                    M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], qv);
                 }
             }
 #pragma unroll
@@ -343,90 +498,121 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                 if (nt >= NTK) continue;
                 colsum[tj] += __shfl_xor(colsum[tj], 16);
                 colsum[tj] += __shfl_xor(colsum[tj], 32);
-                if (q == 0) sS[wr * KPMAX + nt * 16 + l16] = colsum[tj];
+                if (q == 0) sm.s[wr * KP + nt * 16 + l16] = colsum[tj];
             }
         }
-        if constexpr (M::kStageC) {
-            // YC batch into LDS, a-major: sYC[a*SB + t] (zero outside the batch and k)
+        if constexpr (SM::kStageCT) {
+            // YC batch into LDS, a-major: yct[a*SB + t] (zero outside the batch and k)
             for (int e = tid; e < MB * KP; e += kThreads) {
                 const int tr = e / KP, a = e % KP;
-                const Y v = (tr < nb && a < k) ? YC[(size_t)sIdx[tr] * ldy + a] : M::to_op(0.0f);
-                sYC[a * SB + tr] = v;
+                const Y v = (tr < nb && a < k) ? Yv[2][(size_t)sm.idx[tr] * ldy + a] : M::to_op(0.0f);
+                sm.yct[a * SB + tr] = v;
             }
         }
         __syncthreads();
 
         // ================= phase 4: D = YC^T Q (+ rank one), update Phi
         {
-            f32x4 dacc[kTR][TC];
+            constexpr int vc = (NSTAGE == 3) ? 2 : 0;
+            f32x4 dacc[TRK][TC];
 #pragma unroll
-            for (int ti = 0; ti < kTR; ++ti)
+            for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) dacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < MB; k0 += M::KI) {
-                typename M::Frag fa[kTR], fb[TC];
+                typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
-                for (int ti = 0; ti < kTR; ++ti) {
+                for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + 4 * ti;
                     const int a = mt * 16 + l16;
-                    if constexpr (M::kStageC) {
-                        if (mt < NTK) fa[ti] = M::lds(&sYC[a * SB + k0 + q * M::EPL]);
+                    if (mt >= NTK) {
+                        fa[ti] = M::zero_frag();
+                    } else if constexpr (NSTAGE > 0) {
+                        // EPL rows t = k0 + EPL*q + e of column a of the staged batch
+                        if constexpr (M::EPL == 1) {
+                            fa[ti] = sm.ybatch[(vc * kMaxBatch + k0 + q) * SY + a];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < M::EPL; ++e)
+                                fa[ti][e] = sm.ybatch[(vc * kMaxBatch + k0 + q * M::EPL + e) * SY + a];
+                        }
+                    } else if constexpr (SM::kStageCT) {
+                        fa[ti] = M::lds(&sm.yct[a * SB + k0 + q * M::EPL]);
                     } else {
                         const int tr = k0 + q;
-                        fa[ti] = (mt < NTK && a < k && tr < nb) ? YC[(size_t)sIdx[tr] * ldy + a] : 0.0f;
+                        fa[ti] = (a < k && tr < nb) ? Yv[2][(size_t)sm.idx[tr] * ldy + a] : 0.0f;
                     }
                 }
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + 2 * tj;
-                    if (nt < NTK) fb[tj] = M::lds(&sBuf[(nt * 16 + l16) * SB + k0 + q * M::EPL]);
+                    fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
                 }
 #pragma unroll
-                for (int ti = 0; ti < kTR; ++ti)
+                for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj)
                         if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
                             dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
             }
             const float invB = 1.0f / static_cast<float>(nb);
-            const bool snap = (Snap != nullptr) && (s == g.spp - 1);
+            const bool snap = (Snap != nullptr) && (si.s == g.spp - 1);
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + 2 * tj;
                 if (nt >= NTK) continue;
                 const int i = nt * 16 + l16;
-                const float ssum = sS[i] + sS[KPMAX + i] + sS[2 * KPMAX + i] + sS[3 * KPMAX + i];
-                const float rv = g.c * sM[i] * sM[KPMAX + i] - g.b * ssum * invB;
+                const float ssum = sm.s[i] + sm.s[KP + i] + sm.s[2 * KP + i] + sm.s[3 * KP + i];
+                const float rv = g.c * sm.m[i] * sm.m[KP + i] - g.b * ssum * invB;
 #pragma unroll
-                for (int ti = 0; ti < kTR; ++ti) {
+                for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + 4 * ti;
                     if (mt >= NTK) continue;
                     f32x4 v = phi[ti][tj], cv = comp[ti][tj];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int a = mt * 16 + 4 * q + r;
-                        const float d = dacc[ti][tj][r] * invB + sYbar[2 * KPMAX + a] * rv;
+                        const float d = dacc[ti][tj][r] * invB + sm.ybar[2 * KP + a] * rv;
                         const float delta = beta * (d - g.kappa * oacc[ti][tj][r]);
-                        if (g.compensated) {
-                            const float y = delta - cv[r];
-                            const float tt = v[r] + y;
-                            cv[r] = (tt - v[r]) - y;
-                            v[r] = tt;
-                        } else {
-                            v[r] += delta;
-                        }
-                        bad |= !isfinite(v[r]);
-                        if (snap && a < k && i < k)
-                            Snap[(size_t)pass * k * k + (size_t)i * k + a] = v[r];
+                        // Kahan step; cmask = 0 turns it into the plain update
+                        const float y = delta - cv[r];
+                        const float tt = v[r] + y;
+                        cv[r] = ((tt - v[r]) - y) * cmask;
+                        v[r] = tt;
                     }
                     phi[ti][tj] = v;
                     comp[ti][tj] = cv;
-                    M::store4(&sPhi[i * SP + mt * 16 + 4 * q], v);
+                    M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                     if constexpr (M::kPhiT) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) sPhiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
+                        for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
                     }
                 }
+            }
+            if (si.s == g.spp - 1 || t + 1 == g.end_step) {
+                // non-finite values propagate through every later step, so one
+                // check per pass (and at the end of the run) sees any of them
+#pragma unroll
+                for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+                    for (int ti = 0; ti < TRK; ++ti)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) bad |= !isfinite(phi[ti][tj][r]);
+            }
+            if (snap) {   // end of a pass: Phi to the snapshot of this pass
+#pragma unroll
+                for (int tj = 0; tj < TC; ++tj)
+#pragma unroll
+                    for (int ti = 0; ti < TRK; ++ti) {
+                        const int mt = wr + 4 * ti, nt = wc + 2 * tj;
+                        if (mt >= NTK || nt >= NTK) continue;
+                        const int i = nt * 16 + l16;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int a = mt * 16 + 4 * q + r;
+                            if (a < k && i < k) Snap[(size_t)si.pass * k * k + (size_t)i * k + a] = phi[ti][tj][r];
+                        }
+                    }
             }
         }
         __syncthreads();
@@ -434,7 +620,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
 
     // ---- write back the master copy (and compensation)
 #pragma unroll
-    for (int ti = 0; ti < kTR; ++ti)
+    for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
         for (int tj = 0; tj < TC; ++tj) {
             const int mt = wr + 4 * ti, nt = wc + 2 * tj;
@@ -452,10 +638,26 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     if (bad && g.nonfinite) *g.nonfinite = 1;
 }
 
-template <class M, int KPMAX>
+constexpr size_t kLdsLimit = 160 * 1024;
+
+template <class M, int KP, int NSTAGE>
 int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
-    hipLaunchKernelGGL((sgd_kernel<M, KPMAX>), dim3(restarts), dim3(kThreads), 0, st, a);
+    static_assert(smem_bytes<M, KP, NSTAGE>() <= kLdsLimit, "STGD shared memory exceeds 160 KB");
+    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE>), dim3(restarts), dim3(kThreads), 0, st, a);
     return check_launch("sgd_kernel");
+}
+
+// Picks the instantiation: the smallest padded k, then the largest batch
+// staging that fits in LDS (one view when the three views alias).
+template <class M, int KP>
+int dispatch_staging(const SgdArgs& a, int restarts, bool aliased, hipStream_t st) {
+    if constexpr (smem_bytes<M, KP, 3>() <= kLdsLimit) {
+        if (!aliased) return launch_sgd<M, KP, 3>(a, restarts, st);
+    }
+    if constexpr (smem_bytes<M, KP, 1>() <= kLdsLimit) {
+        if (aliased) return launch_sgd<M, KP, 1>(a, restarts, st);
+    }
+    return launch_sgd<M, KP, 0>(a, restarts, st);
 }
 
 int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB, const void* YC,
@@ -472,6 +674,7 @@ int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* Y
     OTM_REQUIRE(p->ldy >= p->k, OTM_ESHAPE, "ldy < k");
     OTM_REQUIRE(p->y_dtype == OTM_F32 || p->y_dtype == OTM_BF16, OTM_EDTYPE, "y_dtype must be F32 or BF16");
     OTM_REQUIRE(p->y_dtype != OTM_BF16 || p->ldy % 8 == 0, OTM_ESHAPE, "BF16 rows need ldy % 8 == 0");
+    OTM_REQUIRE(p->y_dtype != OTM_F32 || p->ldy % 4 == 0, OTM_ESHAPE, "F32 rows need ldy % 4 == 0");
     OTM_REQUIRE(p->beta_tau > 0.0, OTM_EINVAL, "beta_tau must be positive");
     OTM_REQUIRE(std::isfinite(p->beta0) && std::isfinite(p->alpha0) && std::isfinite(p->theta) && p->alpha0 >= 0.0,
                 OTM_EINVAL, "alpha0, beta0, theta must be finite, alpha0 >= 0");
@@ -494,17 +697,26 @@ int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* Y
     a.beta0 = p->beta0;
     a.beta_tau = p->beta_tau;
     if (a.start_step == a.end_step && !Phi_comp) return OTM_OK;
+    const bool aliased = (YA == YB) && (YB == YC);
     const int k = p->k;
     if (p->y_dtype == OTM_F32) {
-        const int kp = (k + 15) / 16 * 16;
-        if (kp <= 32) return launch_sgd<MmaF32, 32>(a, restarts, st);
-        if (kp <= 64) return launch_sgd<MmaF32, 64>(a, restarts, st);
-        return launch_sgd<MmaF32, 128>(a, restarts, st);
+        switch ((k + 15) / 16) {
+            case 1: return dispatch_staging<MmaF32, 16>(a, restarts, aliased, st);
+            case 2: return dispatch_staging<MmaF32, 32>(a, restarts, aliased, st);
+            case 3: return dispatch_staging<MmaF32, 48>(a, restarts, aliased, st);
+            case 4: return dispatch_staging<MmaF32, 64>(a, restarts, aliased, st);
+            case 5: return dispatch_staging<MmaF32, 80>(a, restarts, aliased, st);
+            case 6: return dispatch_staging<MmaF32, 96>(a, restarts, aliased, st);
+            case 7: return dispatch_staging<MmaF32, 112>(a, restarts, aliased, st);
+            default: return dispatch_staging<MmaF32, 128>(a, restarts, aliased, st);
+        }
     }
-    const int kp = (k + 31) / 32 * 32;
-    if (kp <= 32) return launch_sgd<MmaBF16, 32>(a, restarts, st);
-    if (kp <= 64) return launch_sgd<MmaBF16, 64>(a, restarts, st);
-    return launch_sgd<MmaBF16, 128>(a, restarts, st);
+    switch ((k + 31) / 32) {
+        case 1: return dispatch_staging<MmaBF16, 32>(a, restarts, aliased, st);
+        case 2: return dispatch_staging<MmaBF16, 64>(a, restarts, aliased, st);
+        case 3: return dispatch_staging<MmaBF16, 96>(a, restarts, aliased, st);
+        default: return dispatch_staging<MmaBF16, 128>(a, restarts, aliased, st);
+    }
 }
 
 }  // namespace
