@@ -3,13 +3,8 @@
 //  * gemm_tn: C = A^T B for tall A, B (d x p, d x q): split-K partials over row
 //    chunks, then a fixed-order reduction.
 //  * gemm_nn: C = A B with A tall (d x p) and B small (p x q).
-//  * jacobi: cyclic two-sided Jacobi eigensolver for a symmetric n x n matrix
-//    (n <= 256) in one workgroup.  Rounds follow the round-robin tournament
-//    order, so each round applies n/2 disjoint rotations at once: every 2x2
-//    block (rows of pair P, columns of pair Q) becomes R_P^T X R_Q, and the
-//    eigenvector matrix's column pairs rotate by R_P.  A pair is rotated only
-//    while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and |a_pq| > 1e-18 ||A||_F; sweeps
-//    stop after one without any rotation (at most 60).
+//  * eigenproblems of the small symmetric matrices go to the Jacobi solver of
+//    jacobi.hip.
 //  * whitener (Section 3.1; Section 4.2, randomized tall-thin SVD with the
 //    projected matrix truncated to its top k eigenpairs):
 //      Omega = sym(S^T O) -> eig -> B = O U_k sigma_k^(-1/2)
@@ -151,121 +146,7 @@ int gemm_nn(const double* A, int lda, const double* B, int ldb, double* C, int l
     return check_launch("gemm_nn_kernel");
 }
 
-// ------------------------------------------------------------------- jacobi
-constexpr int kJacThreads = 1024;
 constexpr int kJacMaxN = 256;
-
-__device__ __forceinline__ int rr_player(int pos, int round, int N) {
-    if (pos == 0) return 0;
-    return 1 + (pos - 1 + round) % (N - 1);
-}
-
-// A (n x n, symmetric, overwritten), V (n x n, set to the eigenvectors as columns).
-// On exit evals[i] = A[i][i] and order[j] = index of the j-th largest eigenvalue
-// (ties: lower index first).
-__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(double* __restrict__ A, double* __restrict__ V, int n,
-                                                             double* __restrict__ evals, int* __restrict__ order) {
-    __shared__ double sc[kJacMaxN / 2], ss[kJacMaxN / 2];
-    __shared__ int sp[kJacMaxN / 2], sq[kJacMaxN / 2];
-    __shared__ double s_red[kJacThreads / 64];
-    __shared__ double s_fro;
-    __shared__ int s_rotated;
-    const int tid = threadIdx.x;
-    const int N = (n + 1) & ~1;           // even count; index n (if n odd) is a dummy
-    const int npairs = N / 2;
-    // Frobenius norm (invariant under the rotations) for the absolute threshold
-    double f = 0.0;
-    for (int e = tid; e < n * n; e += kJacThreads) {
-        V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
-        f += A[e] * A[e];
-    }
-    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
-    if ((tid & 63) == 0) s_red[tid >> 6] = f;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kJacThreads / 64; ++w) t += s_red[w];
-        s_fro = sqrt(t);
-    }
-    __syncthreads();
-    const double abs_tol = 1e-18 * s_fro;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        if (tid == 0) s_rotated = 0;
-        __syncthreads();
-        for (int round = 0; round < N - 1; ++round) {
-            if (tid < npairs) {
-                int p = rr_player(tid, round, N), q = rr_player(N - 1 - tid, round, N);
-                if (p > q) { const int t = p; p = q; q = t; }
-                double c = 1.0, s = 0.0;
-                if (q < n) {
-                    const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q], apq = A[(size_t)p * n + q];
-                    const bool small = fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= abs_tol;
-                    if (!small) {
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                        s_rotated = 1;
-                    }
-                }
-                sp[tid] = p;
-                sq[tid] = q;
-                sc[tid] = c;
-                ss[tid] = s;
-            }
-            __syncthreads();
-            // two-sided update on 2x2 blocks
-            for (int e = tid; e < npairs * npairs; e += kJacThreads) {
-                const int P = e / npairs, Q = e % npairs;
-                const int p1 = sp[P], q1 = sq[P], p2 = sp[Q], q2 = sq[Q];
-                const double c1 = sc[P], s1 = ss[P], c2 = sc[Q], s2 = ss[Q];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const bool r1ok = q1 < n, r2ok = q2 < n;   // p < q, so only q can be the dummy
-                const double x00 = A[(size_t)p1 * n + p2];
-                const double x01 = r2ok ? A[(size_t)p1 * n + q2] : 0.0;
-                const double x10 = r1ok ? A[(size_t)q1 * n + p2] : 0.0;
-                const double x11 = (r1ok && r2ok) ? A[(size_t)q1 * n + q2] : 0.0;
-                // R = [[c, s], [-s, c]];  X' = R1^T X R2
-                const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
-                const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
-                A[(size_t)p1 * n + p2] = y00 * c2 - y01 * s2;
-                if (r2ok) A[(size_t)p1 * n + q2] = y00 * s2 + y01 * c2;
-                if (r1ok) A[(size_t)q1 * n + p2] = y10 * c2 - y11 * s2;
-                if (r1ok && r2ok) A[(size_t)q1 * n + q2] = y10 * s2 + y11 * c2;
-            }
-            // eigenvector columns
-            for (int e = tid; e < n * npairs; e += kJacThreads) {
-                const int r = e / npairs, P = e % npairs;
-                const int p1 = sp[P], q1 = sq[P];
-                const double c = sc[P], s = ss[P];
-                if (s == 0.0 || q1 >= n) continue;
-                const double vp = V[(size_t)r * n + p1], vq = V[(size_t)r * n + q1];
-                V[(size_t)r * n + p1] = c * vp - s * vq;
-                V[(size_t)r * n + q1] = s * vp + c * vq;
-            }
-            __threadfence_block();
-            __syncthreads();
-        }
-        if (!s_rotated) break;     // a whole sweep without a rotation: converged
-        __syncthreads();
-    }
-    for (int i = tid; i < n; i += kJacThreads) evals[i] = A[(size_t)i * n + i];
-    __syncthreads();
-    for (int i = tid; i < n; i += kJacThreads) {
-        const double v = evals[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double u = evals[j];
-            if (u > v || (u == v && j < i)) ++rank;
-        }
-        order[rank] = i;
-    }
-}
-
-int jacobi(double* A, double* V, int n, double* evals, int* order, hipStream_t s) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kJacThreads), 0, s, A, V, n, evals, order);
-    return check_launch("jacobi_kernel");
-}
 
 // ---------------------------------------------------------------- whitener
 __global__ void symmetrize_kernel(double* __restrict__ A, int n) {
@@ -454,6 +335,8 @@ extern "C" size_t otm_whitener_workspace(int32_t d, int32_t k_tilde, int32_t k) 
     b += part;
     b += ws_round(sizeof(double) * kSignBlocks * k) + ws_round(sizeof(int) * kSignBlocks * k);
     b += ws_round(sizeof(double) * k);                                // signs
+    const size_t j1 = jacobi_ws_bytes(k_tilde), j2 = jacobi_ws_bytes(k);
+    b += j1 > j2 ? j1 : j2;                                           // eigensolver log
     return b;
 }
 
@@ -487,18 +370,20 @@ extern "C" int otm_whitener(const double* O, const double* S, int32_t d, int32_t
     double* pval = wc.take<double>((size_t)kSignBlocks * k);
     int* pidx = wc.take<int>((size_t)kSignBlocks * k);
     double* sgn = wc.take<double>(k);
+    const size_t jb = jacobi_ws_bytes(kt) > jacobi_ws_bytes(k) ? jacobi_ws_bytes(kt) : jacobi_ws_bytes(k);
+    void* jws = wc.take<char>(jb);
     int st;
     if ((st = gemm_tn(S, kt, O, kt, d, kt, kt, Om, part, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((kt * kt + 255) / 256), dim3(256), 0, s, Om, kt);
     if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
-    if ((st = jacobi(Om, Vo, kt, ev, ord, s)) != OTM_OK) return st;
+    if ((st = jacobi(Om, Vo, kt, ev, ord, jws, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(top_k_scale_kernel, dim3((kt * k + 255) / 256), dim3(256), 0, s, Vo, ev, ord, kt, k, Pk, info);
     if ((st = check_launch("top_k_scale_kernel")) != OTM_OK) return st;
     if ((st = gemm_nn(O, kt, Pk, k, Bm, k, d, kt, k, s)) != OTM_OK) return st;
     if ((st = gemm_tn(Bm, k, Bm, k, d, k, k, Gr, part, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Gr, k);
     if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
-    if ((st = jacobi(Gr, Vb, k, evb, ordb, s)) != OTM_OK) return st;
+    if ((st = jacobi(Gr, Vb, k, evb, ordb, jws, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(whiten_scale_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Vb, evb, ordb, k, info, Pw,
                        evals);
     if ((st = check_launch("whiten_scale_kernel")) != OTM_OK) return st;
@@ -518,6 +403,7 @@ extern "C" size_t otm_orthonormalize_workspace(int32_t d, int32_t m) {
     size_t b = ws_round(sizeof(double) * (size_t)m * m) * 3;   // Gram, V, Pq
     b += ws_round(sizeof(double) * m) + ws_round(sizeof(int) * m);
     b += gemm_tn_ws(d, m, m);
+    b += jacobi_ws_bytes(m);
     return b;
 }
 
@@ -536,11 +422,12 @@ extern "C" int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double*
     double* ev = wc.take<double>(m);
     int* ord = wc.take<int>(m);
     double* part = wc.take<double>(gemm_tn_ws(d, m, m) / sizeof(double));
+    void* jws = wc.take<char>(jacobi_ws_bytes(m));
     int st;
     if ((st = gemm_tn(Y, m, Y, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, Gr, m);
     if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
-    if ((st = jacobi(Gr, V, m, ev, ord, s)) != OTM_OK) return st;
+    if ((st = jacobi(Gr, V, m, ev, ord, jws, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(orth_scale_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, V, ev, m, Pq, info);
     if ((st = check_launch("orth_scale_kernel")) != OTM_OK) return st;
     return gemm_nn(Y, m, Pq, m, Q, m, d, m, m, s);
@@ -554,6 +441,7 @@ extern "C" size_t otm_unwhiten_workspace(int32_t d, int32_t k) {
     b += gemm_tn_ws(d, k, k);
     b += ws_round(sizeof(double) * (size_t)kColBlocks * k);
     b += ws_round(sizeof(double) * k);
+    b += jacobi_ws_bytes(k);
     return b;
 }
 
@@ -577,6 +465,7 @@ extern "C" int otm_unwhiten_topics(const double* W, int32_t d, int32_t k, const 
     double* part = wc.take<double>(gemm_tn_ws(d, k, k) / sizeof(double));
     double* cpart = wc.take<double>((size_t)kColBlocks * k);
     double* csum = wc.take<double>(k);
+    void* jws = wc.take<char>(jacobi_ws_bytes(k));
     int st;
     hipLaunchKernelGGL(factor_stats_kernel, dim3(1), dim3(kMaxK), 0, s, Phi, k, 0.5 * (1.0 + theta), lambda, UL,
                        alpha_hat);
@@ -584,7 +473,7 @@ extern "C" int otm_unwhiten_topics(const double* W, int32_t d, int32_t k, const 
     if ((st = gemm_tn(W, k, W, k, d, k, k, Gr, part, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, Gr, k);
     if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
-    if ((st = jacobi(Gr, V, k, ev, ord, s)) != OTM_OK) return st;
+    if ((st = jacobi(Gr, V, k, ev, ord, jws, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(spd_inverse_kernel, dim3((k * k + 255) / 256), dim3(256), 0, s, V, ev, k, Gi, info);
     if ((st = check_launch("spd_inverse_kernel")) != OTM_OK) return st;
     if ((st = gemm_nn(Gi, k, UL, k, Z, k, k, k, k, s)) != OTM_OK) return st;

@@ -43,6 +43,12 @@ inline size_t ws_round(size_t bytes) { return (bytes + 255) & ~size_t(255); }
 
 int validate_csr_header(const otm_csr* C, const char* name);
 
+// Symmetric FP64 eigensolver for n <= 256 (jacobi.hip): A (n x n, overwritten),
+// V (n x n, eigenvectors as columns), evals[i] = eigenvalue of column i,
+// order[j] = column of the j-th largest eigenvalue.  ws: jacobi_ws_bytes(n).
+size_t jacobi_ws_bytes(int n);
+int jacobi(double* A, double* V, int n, double* evals, int* order, void* ws, hipStream_t s);
+
 // ------------------------------------------------------------- numerics
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

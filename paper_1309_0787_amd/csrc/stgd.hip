@@ -27,7 +27,8 @@
 // the rows from global memory inside the products.
 //
 // Four workgroup barriers per step: after G*G, after O (the buffer then
-// takes Q), after Q, after the update.
+// takes Q), after Q, after the update.  The batch is padded to 128 rows in
+// every product, so every tile loop has a compile-time trip count.
 #include <cmath>
 
 #include "otm_internal.h"
@@ -47,7 +48,6 @@ struct MmaF32 {
     using Chunk = f32x4;                      // 16-byte row piece of the batch
     static constexpr int KI = 4;
     static constexpr int EPL = 1;
-    static constexpr int KMUL = 16;           // padding multiple of k and of the batch
     static constexpr int SPAD = 4;            // LDS row padding (elements)
     static constexpr int CH = 4;              // elements per chunk
     static constexpr bool kPhiT = false;
@@ -81,7 +81,6 @@ struct MmaBF16 {
     using Chunk = bf16x8;
     static constexpr int KI = 32;
     static constexpr int EPL = 8;
-    static constexpr int KMUL = 32;
     static constexpr int SPAD = 8;
     static constexpr int CH = 8;
     static constexpr bool kPhiT = true;
@@ -138,29 +137,31 @@ struct SgdArgs {
     float* snapshots;
     int32_t* nonfinite;
     int32_t n, k, batch, passes, ldy, compensated;
-    int64_t start_step, end_step, spp;
+    int32_t start_step, end_step, spp;
     float a, b, c, kappa;
-    double beta0, beta_tau;
+    float beta0, inv_tau;
 };
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTR = 2;  // tile rows per wave (4 wave rows x 2 = 8 tiles = 128)
+constexpr int MB = kMaxBatch;           // batch rows padded to 128 in every product
+constexpr int NTM = MB / 16;            // batch tiles
+constexpr int kTR = NTM / 4;            // batch tile rows per wave
 
 template <class M, int KP, int NSTAGE>
 struct SgdSmem {
     using Op = typename M::Op;
     using Y = typename M::Y;
     static constexpr int SP = KP + M::SPAD;        // Phi rows
-    static constexpr int SB = kMaxBatch + M::SPAD;    // exchange buffer rows (t or j)
+    static constexpr int SB = MB + M::SPAD;        // exchange buffer rows (t or j)
     static constexpr int SY = KP + M::SPAD;        // staged batch rows
     static constexpr bool kStageCT = (NSTAGE == 0) && M::kPhiT;   // BF16 fallback: YC batch a-major
     alignas(16) Op phi[KP * SP];
     alignas(16) Op phiT[M::kPhiT ? KP * SP : 1];
     alignas(16) Op buf[KP * SB];
-    alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * kMaxBatch * SY : 1];
+    alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * MB * SY : 1];
     alignas(16) Op yct[kStageCT ? KP * SB : 1];
-    alignas(16) int32_t idx[kMaxBatch];
+    alignas(16) int32_t idx[MB];
     alignas(16) float ybar[3 * KP];
     alignas(16) float m[2 * KP];
     alignas(16) float s[4 * KP];
@@ -168,20 +169,6 @@ struct SgdSmem {
 
 template <class M, int KP, int NSTAGE>
 constexpr size_t smem_bytes() { return sizeof(SgdSmem<M, KP, NSTAGE>); }
-
-struct StepInfo {
-    int64_t pass;
-    int s, row0, nb;
-};
-
-__device__ __forceinline__ StepInfo step_info(const SgdArgs& g, int64_t t) {
-    StepInfo si;
-    si.pass = t / g.spp;
-    si.s = static_cast<int>(t - si.pass * g.spp);
-    si.row0 = si.s * g.batch;
-    si.nb = min(g.batch, g.n - si.row0);
-    return si;
-}
 
 template <class M, int KP, int NSTAGE>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
@@ -192,8 +179,9 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     constexpr int TC = (NTK + 1) / 2;              // tile columns per wave
     constexpr int TRK = (NTK + 3) / 4;             // tile rows per wave in the k x k products
     constexpr int SP = SM::SP, SB = SM::SB, SY = SM::SY;
-    // batch chunks per thread (16 bytes each) when staging
-    constexpr int NCH = (kMaxBatch * KP / M::CH + kThreads - 1) / kThreads;
+    constexpr int cpr = KP / M::CH;                // 16-byte chunks per batch row
+    constexpr int NCH = (MB * cpr + kThreads - 1) / kThreads;   // chunks per thread when staging
+    constexpr int UNR = (M::KI >= 32) ? 4 : 2;     // unroll of the contraction loops
     __shared__ __attribute__((aligned(16))) SM sm;
 
     const int tid = threadIdx.x;
@@ -204,9 +192,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     const int l16 = lane & 15, q = lane >> 4;
 
     const int k = g.k;
-    const int MB = (g.batch + M::KMUL - 1) / M::KMUL * M::KMUL;
-    const int NTM = MB / 16;
-    const int n = g.n, ldy = g.ldy;
+    const int n = g.n, ldy = g.ldy, B = g.batch;
     const int r_id = blockIdx.x;
     float* Phi = g.Phi + (size_t)r_id * k * k;
     float* Comp = g.Phi_comp ? g.Phi_comp + (size_t)r_id * k * k : nullptr;
@@ -215,8 +201,11 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     const Y* Yv[3] = {static_cast<const Y*>(g.YA), static_cast<const Y*>(g.YB), static_cast<const Y*>(g.YC)};
     bool bad = false;
     const float cmask = g.compensated ? 1.0f : 0.0f;
-    const float beta0f = static_cast<float>(g.beta0);
-    const float inv_tauf = static_cast<float>(1.0 / g.beta_tau);
+    // mA = Phi^T ybarA and mB = Phi^T ybarB ride along in Phi^T Phi when two
+    // padding rows are free: the phi_i-major operand holds ybarA, ybarB as
+    // "components" k and k+1 (never updated, zero in the a-major copy), so
+    // G[i][k] = mA[i] and G[i][k+1] = mB[i].
+    const bool mfold = (k + 2 <= KP);
 
     // ---- master copy of Phi in registers: tile (mt, nt) holds a = row, i = column
     f32x4 phi[TRK][TC], comp[TRK][TC];
@@ -234,12 +223,15 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     if (a < k && i < k) {
                         v[r] = Phi[(size_t)i * k + a];
                         if (Comp && g.compensated) cv[r] = Comp[(size_t)i * k + a];
+                    } else if (mfold && a < k && (i == k || i == k + 1)) {
+                        v[r] = g.ybar[(i - k) * k + a];
                     }
                 }
                 M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                 if constexpr (M::kPhiT) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
+                    for (int r = 0; r < 4; ++r)
+                        sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(i < k ? v[r] : 0.0f);
                 }
             }
             phi[ti][tj] = v;
@@ -249,23 +241,28 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
         const int v = e / KP, a = e % KP;
         sm.ybar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
     }
+    // per-column factor of the update: 1 for a live component, 0 for padding
+    float live[TC];
+#pragma unroll
+    for (int tj = 0; tj < TC; ++tj) live[tj] = ((wc + 2 * tj) * 16 + l16 < k) ? 1.0f : 0.0f;
 
     // ---- batch prefetch state (NSTAGE > 0)
-    constexpr int cpr = KP / M::CH;                 // chunks per row
     int32_t pidx[NCH];
     typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
-    auto issue_index = [&](int64_t t) {
+    auto issue_index = [&](int t) {
         if constexpr (NSTAGE > 0) {
-            const bool live = t < g.end_step;
-            StepInfo si;
-            if (live) si = step_info(g, t);
+            const bool live_step = t < g.end_step;
+            const int pass = live_step ? t / g.spp : 0;
+            const int row0 = live_step ? (t - pass * g.spp) * B : 0;
+            const int nb = live_step ? min(B, n - row0) : 0;
+            const int32_t* pp = perms ? perms + (size_t)pass * n + row0 : nullptr;
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
                 const int tr = c / cpr;
                 int32_t r = -1;
-                if (live && c < MB * cpr && tr < si.nb) {
-                    r = perms ? perms[(size_t)si.pass * n + si.row0 + tr] : si.row0 + tr;
+                if (c < MB * cpr && tr < nb) {
+                    r = pp ? pp[tr] : row0 + tr;
                     if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
                         r = 0;
                         bad = true;
@@ -298,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     const int tr = c / cpr, a0 = (c % cpr) * M::CH;
 #pragma unroll
                     for (int v = 0; v < NSTAGE; ++v)
-                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * kMaxBatch + tr) * SY + a0]) = pbuf[v][j];
+                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * MB + tr) * SY + a0]) = pbuf[v][j];
                 }
             }
         }
@@ -307,17 +304,19 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     issue_data();
     __syncthreads();
 
-    for (int64_t t = g.start_step; t < g.end_step; ++t) {
-        const StepInfo si = step_info(g, t);
-        const int nb = si.nb;
-        const float beta = beta0f / (1.0f + static_cast<float>(t) * inv_tauf);
+    for (int t = g.start_step; t < g.end_step; ++t) {
+        const int pass = t / g.spp;
+        const int s = t - pass * g.spp;
+        const int row0 = s * B;
+        const int nb = min(B, n - row0);
+        const float beta = g.beta0 / (1.0f + static_cast<float>(t) * g.inv_tau);
 
-        // ================= phase 1: batch rows, mA/mB, G = Phi^T Phi -> G*G
+        // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
         commit();
         issue_index(t + 1);
         if constexpr (NSTAGE == 0) {
             if (tid < nb) {
-                int32_t r = perms ? perms[(size_t)si.pass * n + si.row0 + tid] : si.row0 + tid;
+                int32_t r = perms ? perms[(size_t)pass * n + row0 + tid] : row0 + tid;
                 if (r < 0 || r >= n) {
                     r = 0;
                     bad = true;
@@ -325,15 +324,15 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                 sm.idx[tid] = r;
             }
         }
-        {
-            // mA, mB: thread (view v, column i, half h) sums half of a dot product
+        if (!mfold) {
+            // mA, mB on the vector ALU: thread (view v, column i, half h) sums half a dot product
             const int v = tid >> 8, rem = tid & 255, i = rem >> 1, h = rem & 1;
             float acc = 0.f;
             if (i < KP) {
-                const int half = KP >> 1;
+                constexpr int half = KP >> 1;
                 const Op* prow = &sm.phi[i * SP + h * half];
                 const float* yb = &sm.ybar[v * KP + h * half];
-#pragma unroll 4
+#pragma unroll
                 for (int a = 0; a < half; a += 8) {
                     float x[8];
                     if constexpr (M::EPL == 8) {
@@ -360,6 +359,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll UNR
             for (int k0 = 0; k0 < KP; k0 += M::KI) {
                 typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
@@ -379,15 +379,19 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                         if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
                             acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
             }
-            // G*G into the exchange buffer, column-major: buf[i*SB + j] = G[j][i]^2
+            // G*G into the exchange buffer, column-major: buf[i*SB + j] = G[j][i]^2;
+            // the columns k, k+1 of G give mA, mB when folded
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int mt = wr + 4 * ti, nt = wc + 2 * tj;
                     if (mt < NTK && nt < NTK) {
-                        f32x4 v = acc[ti][tj] * acc[ti][tj];
-                        M::store4(&sm.buf[(nt * 16 + l16) * SB + mt * 16 + 4 * q], v);
+                        const int i = nt * 16 + l16;
+                        const f32x4 gv = acc[ti][tj];
+                        M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], gv * gv);
+                        if (mfold && (i == k || i == k + 1))
+                            *reinterpret_cast<f32x4*>(&sm.m[(i - k) * KP + mt * 16 + 4 * q]) = gv;
                     }
                 }
         }
@@ -399,6 +403,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
         for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) oacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll UNR
         for (int k0 = 0; k0 < KP; k0 += M::KI) {
             typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                 const int a = mt * 16 + l16;
                 if (mt < NTK) {
                     if constexpr (M::kPhiT) fa[ti] = M::lds(&sm.phiT[a * SP + k0 + q * M::EPL]);
-                    else fa[ti] = sm.phi[(k0 + q) * SP + a];
+                    else fa[ti] = (k0 + q < k) ? sm.phi[(k0 + q) * SP + a] : 0.0f;   // a-major view, live columns
                 } else {
                     fa[ti] = M::zero_frag();
                 }
@@ -432,13 +437,22 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
         // ================= phase 3: PA, PB one tile row at a time -> Q into the
         // exchange buffer (buf[i*SB + t] = Q[t][i]) and column sums of H
         {
+            // per column: Q = al*xa*xb - bmB*xa - bmA*xb with the padding mask folded in
             float colsum[TC];
+            float al[TC], bmA[TC], bmB[TC];
 #pragma unroll
-            for (int tj = 0; tj < TC; ++tj) colsum[tj] = 0.f;
+            for (int tj = 0; tj < TC; ++tj) {
+                colsum[tj] = 0.f;
+                const int i = (wc + 2 * tj) * 16 + l16;
+                const float mA = (wc + 2 * tj < NTK) ? sm.m[i] : 0.f;
+                const float mB = (wc + 2 * tj < NTK) ? sm.m[KP + i] : 0.f;
+                al[tj] = g.a * live[tj];
+                bmA[tj] = g.b * live[tj] * mA;
+                bmB[tj] = g.b * live[tj] * mB;
+            }
 #pragma unroll
             for (int ti = 0; ti < kTR; ++ti) {
                 const int mt = wr + 4 * ti;
-                if (mt >= NTM) continue;
                 const int tr = mt * 16 + l16;
                 const Y* rowA = nullptr;
                 const Y* rowB = nullptr;
@@ -448,13 +462,14 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     rowB = ok ? Yv[1] + (size_t)sm.idx[tr] * ldy : nullptr;
                 }
                 const Y* sA = &sm.ybatch[tr * SY];
-                const Y* sB = &sm.ybatch[((NSTAGE == 3 ? 1 : 0) * kMaxBatch + tr) * SY];
+                const Y* sB = &sm.ybatch[((NSTAGE == 3 ? 1 : 0) * MB + tr) * SY];
                 f32x4 pa[TC], pb[TC];
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     pa[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                     pb[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
+#pragma unroll UNR
                 for (int k0 = 0; k0 < KP; k0 += M::KI) {
                     typename M::Frag fa, fbv;
                     if constexpr (NSTAGE == 0) {
@@ -462,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                         fbv = M::yrow(rowB, k0 + q * M::EPL, k);
                     } else {
                         fa = M::lds(sA + k0 + q * M::EPL);
-                        fbv = (NSTAGE == 1) ? fa : M::lds(sB + k0 + q * M::EPL);
+                        if constexpr (NSTAGE == 3) fbv = M::lds(sB + k0 + q * M::EPL);
                     }
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
@@ -470,8 +485,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                         if (nt < NTK) {
                             const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
                             pa[tj] = M::mma(fa, fphi, pa[tj]);
-                            if (NSTAGE == 1) pb[tj] = pa[tj];
-                            else pb[tj] = M::mma(fbv, fphi, pb[tj]);
+                            if constexpr (NSTAGE != 1) pb[tj] = M::mma(fbv, fphi, pb[tj]);
                         }
                     }
                 }
@@ -480,14 +494,18 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     const int nt = wc + 2 * tj;
                     if (nt >= NTK) continue;
                     const int i = nt * 16 + l16;
-                    const float mA = sm.m[i], mB = sm.m[KP + i];
                     f32x4 qv;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float xa = pa[tj][r], xb = pb[tj][r];
-                        const float h = xa * xb;
-                        colsum[tj] += h;
-                        qv[r] = g.a * h - g.b * xa * mB - g.b * mA * xb;
+                        const float xa = pa[tj][r];
+                        if constexpr (NSTAGE == 1) {   // one view: xb = xa
+                            colsum[tj] = fmaf(xa, xa, colsum[tj]);
+                            qv[r] = xa * fmaf(al[tj], xa, -(bmA[tj] + bmB[tj]));
+                        } else {
+                            const float xb = pb[tj][r];
+                            colsum[tj] = fmaf(xa, xb, colsum[tj]);
+                            qv[r] = fmaf(xa, fmaf(al[tj], xb, -bmB[tj]), -bmA[tj] * xb);
+                        }
                     }
                     M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], qv);
                 }
@@ -519,6 +537,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) dacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll UNR
             for (int k0 = 0; k0 < MB; k0 += M::KI) {
                 typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
@@ -530,11 +549,11 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     } else if constexpr (NSTAGE > 0) {
                         // EPL rows t = k0 + EPL*q + e of column a of the staged batch
                         if constexpr (M::EPL == 1) {
-                            fa[ti] = sm.ybatch[(vc * kMaxBatch + k0 + q) * SY + a];
+                            fa[ti] = sm.ybatch[(vc * MB + k0 + q) * SY + a];
                         } else {
 #pragma unroll
                             for (int e = 0; e < M::EPL; ++e)
-                                fa[ti][e] = sm.ybatch[(vc * kMaxBatch + k0 + q * M::EPL + e) * SY + a];
+                                fa[ti][e] = sm.ybatch[(vc * MB + k0 + q * M::EPL + e) * SY + a];
                         }
                     } else if constexpr (SM::kStageCT) {
                         fa[ti] = M::lds(&sm.yct[a * SB + k0 + q * M::EPL]);
@@ -556,7 +575,6 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                             dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
             }
             const float invB = 1.0f / static_cast<float>(nb);
-            const bool snap = (Snap != nullptr) && (si.s == g.spp - 1);
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + 2 * tj;
@@ -564,16 +582,18 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                 const int i = nt * 16 + l16;
                 const float ssum = sm.s[i] + sm.s[KP + i] + sm.s[2 * KP + i] + sm.s[3 * KP + i];
                 const float rv = g.c * sm.m[i] * sm.m[KP + i] - g.b * ssum * invB;
+                // delta = beta*live*(dacc/B + ybarC*rv - kappa*O), folded per column
+                const float bl = beta * live[tj];
+                const float f1 = bl * invB, f2 = bl * rv, f3 = bl * g.kappa;
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + 4 * ti;
                     if (mt >= NTK) continue;
+                    const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
                     f32x4 v = phi[ti][tj], cv = comp[ti][tj];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int a = mt * 16 + 4 * q + r;
-                        const float d = dacc[ti][tj][r] * invB + sm.ybar[2 * KP + a] * rv;
-                        const float delta = beta * (d - g.kappa * oacc[ti][tj][r]);
+                        const float delta = fmaf(f1, dacc[ti][tj][r], fmaf(f2, ybc[r], -f3 * oacc[ti][tj][r]));
                         // Kahan step; cmask = 0 turns it into the plain update
                         const float y = delta - cv[r];
                         const float tt = v[r] + y;
@@ -585,11 +605,11 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
                     M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                     if constexpr (M::kPhiT) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r]);
+                        for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r] * live[tj]);
                     }
                 }
             }
-            if (si.s == g.spp - 1 || t + 1 == g.end_step) {
+            if (s == g.spp - 1 || t + 1 == g.end_step) {
                 // non-finite values propagate through every later step, so one
                 // check per pass (and at the end of the run) sees any of them
 #pragma unroll
@@ -599,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) bad |= !isfinite(phi[ti][tj][r]);
             }
-            if (snap) {   // end of a pass: Phi to the snapshot of this pass
+            if (Snap != nullptr && s == g.spp - 1) {   // end of a pass: Phi to the snapshot of this pass
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj)
 #pragma unroll
@@ -610,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int a = mt * 16 + 4 * q + r;
-                            if (a < k && i < k) Snap[(size_t)si.pass * k * k + (size_t)i * k + a] = phi[ti][tj][r];
+                            if (a < k && i < k) Snap[(size_t)pass * k * k + (size_t)i * k + a] = phi[ti][tj][r];
                         }
                     }
             }
@@ -683,19 +703,22 @@ int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* Y
     a.Phi = Phi; a.Phi_comp = Phi_comp; a.snapshots = snapshots; a.nonfinite = nonfinite;
     a.n = n; a.k = p->k; a.batch = p->batch; a.passes = p->passes; a.ldy = p->ldy;
     a.compensated = p->compensated ? 1 : 0;
-    a.spp = (n + p->batch - 1) / p->batch;
-    const int64_t total = a.spp * p->passes;
-    a.start_step = start_step;
-    a.end_step = end_step < 0 ? total : end_step;
-    OTM_REQUIRE(a.start_step >= 0 && a.start_step <= a.end_step && a.end_step <= total, OTM_ESHAPE,
+    const int64_t spp = (n + p->batch - 1) / p->batch;
+    const int64_t total = spp * p->passes;
+    OTM_REQUIRE(total < (int64_t(1) << 31), OTM_ECAPACITY, "passes * ceil(n / batch) must be < 2^31");
+    const int64_t end = end_step < 0 ? total : end_step;
+    OTM_REQUIRE(start_step >= 0 && start_step <= end && end <= total, OTM_ESHAPE,
                 "need 0 <= start_step <= end_step <= passes * ceil(n / batch)");
+    a.spp = static_cast<int32_t>(spp);
+    a.start_step = static_cast<int32_t>(start_step);
+    a.end_step = static_cast<int32_t>(end);
     const double al = p->alpha0;
     a.a = static_cast<float>((al + 1.0) * (al + 2.0) / 2.0);
     a.b = static_cast<float>(al * (al + 1.0) / 2.0);
     a.c = static_cast<float>(al * al);
     a.kappa = static_cast<float>(0.5 * (1.0 + p->theta));
-    a.beta0 = p->beta0;
-    a.beta_tau = p->beta_tau;
+    a.beta0 = static_cast<float>(p->beta0);
+    a.inv_tau = static_cast<float>(1.0 / p->beta_tau);
     if (a.start_step == a.end_step && !Phi_comp) return OTM_OK;
     const bool aliased = (YA == YB) && (YB == YC);
     const int k = p->k;
