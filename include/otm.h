@@ -118,10 +118,11 @@ int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, i
  * k_tilde = 2k when M2's noise directions dominate the sketch, so the sketch
  * is refined by q steps Q <- orth(M2 Q) before the whitener, as in the power
  * method sketches of the cited Nystrom analysis; q = 0 is the paper's
- * algorithm).  Q = Y (Y^T Y)^(-1/2), d x m FP64, via a Jacobi eigensolver of
- * the m x m Gram.  info: device int32, 0 on success, 1 if Y is rank deficient
- * (Gram eigenvalue <= 1e-14 of the largest).  m <= min(d, 256); Y, Q must not
- * alias. */
+ * algorithm).  Q (d x m FP64) is an orthonormal basis of span(Y): Cholesky
+ * QR applied twice for m <= 200 (Q = Y R1^-1 R2^-1), else Y (Y^T Y)^(-1/2)
+ * through a Jacobi eigensolver of the m x m Gram.  info: device int32, 0 on
+ * success, 1 if Y is rank deficient (a pivot or eigenvalue <= 1e-14 of the
+ * largest).  m <= min(d, 256); Y, Q must not alias. */
 size_t otm_orthonormalize_workspace(int32_t d, int32_t m);
 int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double* Q, int32_t* info,
                        void* ws, size_t ws_bytes, otm_stream stream);

@@ -10,8 +10,9 @@
 //      Omega = sym(S^T O) -> eig -> B = O U_k sigma_k^(-1/2)
 //      B^T B = V_B diag(s^2) V_B^T -> W = B V_B diag(s^-2) = U_B diag(s)^-1
 //      and every column of W turned so that its largest |entry| is positive.
-//  * orthonormalize: Q = Y (Y^T Y)^(-1/2), an orthonormal basis of span(Y), for
-//    the power iterations of the sketch.
+//  * orthonormalize: an orthonormal basis Q of span(Y) for the power iterations
+//    of the sketch, by Cholesky QR applied twice (m <= 200), else
+//    Y (Y^T Y)^(-1/2) through the eigensolver.
 //  * unwhiten_topics (Lemma postprocessing).
 #include <cmath>
 
@@ -245,6 +246,75 @@ __global__ void orth_scale_kernel(const double* __restrict__ V, const double* __
     Pq[e] = ok ? V[e] / sqrt(ev[j]) : 0.0;
 }
 
+// Cholesky of an m x m Gram G = L L^T held in LDS (packed lower triangle,
+// m <= 200) and Rinv = (L^T)^(-1), upper triangular, m x m row-major, so that
+// Y Rinv has orthonormal columns.  info = 1 (pass 0) or |= 1 (pass 1) when a
+// pivot is not above 1e-14 of the largest diagonal entry; that pivot is then
+// replaced by the largest diagonal entry so the results stay finite.
+constexpr int kCholN = 200;
+constexpr int kCholThreads = 1024;
+
+__device__ __forceinline__ int low_idx(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* __restrict__ G, int m,
+                                                                 double* __restrict__ Rinv, int32_t* info, int pass) {
+    __shared__ double sL[kCholN * (kCholN + 1) / 2];
+    __shared__ double s_dmax;
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * m; e += kCholThreads) {
+        const int i = e / m, j = e % m;
+        if (j <= i) sL[low_idx(i, j)] = 0.5 * (G[e] + G[(size_t)j * m + i]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double dm = 0.0;
+        for (int i = 0; i < m; ++i) dm = fmax(dm, sL[low_idx(i, i)]);
+        s_dmax = dm;
+        s_bad = 0;
+    }
+    __syncthreads();
+    const double dmax = s_dmax;
+    for (int j = 0; j < m; ++j) {
+        if (tid == 0) {
+            double dj = sL[low_idx(j, j)];
+            if (!(dj > 1e-14 * dmax)) {
+                s_bad = 1;
+                dj = dmax > 0.0 ? dmax : 1.0;
+            }
+            sL[low_idx(j, j)] = sqrt(dj);
+        }
+        __syncthreads();
+        const double ljj = sL[low_idx(j, j)];
+        for (int i = j + 1 + tid; i < m; i += kCholThreads) sL[low_idx(i, j)] /= ljj;
+        __syncthreads();
+        // trailing update A[i][l] -= L[i][j] L[l][j] for j < l <= i; S threads per row
+        const int w = m - j - 1;
+        if (w > 0) {
+            const int S = max(1, kCholThreads / w);
+            const int row = tid / S, sub = tid % S;
+            if (row < w) {
+                const int i = j + 1 + row;
+                const double lij = sL[low_idx(i, j)];
+                for (int l = j + 1 + sub; l <= i; l += S) sL[low_idx(i, l)] -= lij * sL[low_idx(l, j)];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && (pass == 0 || s_bad)) *info = s_bad;
+    // column c of L^-1 = row c of Rinv: x_c = 1/L_cc, x_i = -(sum_{l=c}^{i-1} L_il x_l) / L_ii
+    for (int c = tid; c < m; c += kCholThreads) {
+        double* x = Rinv + (size_t)c * m;
+        for (int i = 0; i < c; ++i) x[i] = 0.0;
+        x[c] = 1.0 / sL[low_idx(c, c)];
+        for (int i = c + 1; i < m; ++i) {
+            double acc = 0.0;
+            for (int l = c; l < i; ++l) acc += sL[low_idx(i, l)] * x[l];
+            x[i] = -acc / sL[low_idx(i, i)];
+        }
+    }
+}
+
 // ------------------------------------------------------------- unwhitening
 // lambda_i = kappa ||phi_i||^3, UL[a][i] = lambda_i u_i[a], alpha_hat
 __global__ void factor_stats_kernel(const float* __restrict__ Phi, int k, double kappa, double* __restrict__ lam,
@@ -400,9 +470,10 @@ extern "C" int otm_whitener(const double* O, const double* S, int32_t d, int32_t
 
 extern "C" size_t otm_orthonormalize_workspace(int32_t d, int32_t m) {
     if (d < 1 || m < 1) return 0;
-    size_t b = ws_round(sizeof(double) * (size_t)m * m) * 3;   // Gram, V, Pq
+    size_t b = ws_round(sizeof(double) * (size_t)m * m) * 3;   // Gram, V / Rinv, Pq
     b += ws_round(sizeof(double) * m) + ws_round(sizeof(int) * m);
     b += gemm_tn_ws(d, m, m);
+    b += ws_round(sizeof(double) * (size_t)d * m);               // first Cholesky-QR pass
     b += jacobi_ws_bytes(m);
     return b;
 }
@@ -422,8 +493,22 @@ extern "C" int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double*
     double* ev = wc.take<double>(m);
     int* ord = wc.take<int>(m);
     double* part = wc.take<double>(gemm_tn_ws(d, m, m) / sizeof(double));
+    double* Q1 = wc.take<double>((size_t)d * m);
     void* jws = wc.take<char>(jacobi_ws_bytes(m));
     int st;
+    if (m <= kCholN) {
+        // Cholesky QR twice: Q1 = Y R1^-1, Q = Q1 R2^-1 with R^T R the Gram of each input
+        const double* src = Y;
+        for (int pass = 0; pass < 2; ++pass) {
+            double* dst = pass == 0 ? Q1 : Q;
+            if ((st = gemm_tn(src, m, src, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
+            hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), 0, s, Gr, m, V, info, pass);
+            if ((st = check_launch("chol_rinv_kernel")) != OTM_OK) return st;
+            if ((st = gemm_nn(src, m, V, m, dst, m, d, m, m, s)) != OTM_OK) return st;
+            src = Q1;
+        }
+        return OTM_OK;
+    }
     if ((st = gemm_tn(Y, m, Y, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, Gr, m);
     if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
