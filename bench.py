@@ -164,7 +164,8 @@ def main():
                    "precision": "BF16 W/Y and STGD contractions, FP32 accumulate and master, FP64 sketch/whitener/post"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16, "traffic": counters_traffic(),
-                     "kernel": "sgd_kernel<MmaBF16,128>", "flops_per_launch": flops, "launch_ms": sgd_ms},
+                     "kernel": "sgd_kernel<MmaBF16,128>", "flops_per_launch": flops, "launch_ms": sgd_ms,
+                     "frac_one_cu": achieved / (PEAK_BF16 / 256)},
         "stage_ms": {kname: round(v, 4) for kname, v in stages.items()},
         "sgd_samples_per_s": n * w["passes"] / (sgd_ms * 1e-3),
         "sgd_us_per_step": sgd_ms * 1e3 / (w["passes"] * ((n + w["batch"] - 1) // w["batch"])),

@@ -120,7 +120,7 @@ int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, i
  * method sketches of the cited Nystrom analysis; q = 0 is the paper's
  * algorithm).  Q (d x m FP64) is an orthonormal basis of span(Y): Cholesky
  * QR applied twice for m <= 200 (Q = Y R1^-1 R2^-1), else Y (Y^T Y)^(-1/2)
- * through a Jacobi eigensolver of the m x m Gram.  info: device int32, 0 on
+ * through a Jacobi eigensolver of the m x m Gram, also applied twice.  info: device int32, 0 on
  * success, 1 if Y is rank deficient (a pivot or eigenvalue <= 1e-14 of the
  * largest).  m <= min(d, 256); Y, Q must not alias. */
 size_t otm_orthonormalize_workspace(int32_t d, int32_t m);

@@ -232,15 +232,16 @@ __global__ void apply_sign_kernel(double* __restrict__ W, const double* __restri
 }
 
 // Pq[:, j] = V[:, j] / sqrt(ev[j]) for the orthonormal basis Y (Y^T Y)^(-1/2);
-// info = 1 if an eigenvalue of the Gram is not positive enough (rank deficient)
+// info = 1 if an eigenvalue of the Gram is not positive enough (rank deficient);
+// written on pass 0, or-ed on pass 1
 __global__ void orth_scale_kernel(const double* __restrict__ V, const double* __restrict__ ev, int m,
-                                  double* __restrict__ Pq, int32_t* info) {
+                                  double* __restrict__ Pq, int32_t* info, int pass) {
     double emax = 0.0;
     for (int j = 0; j < m; ++j) emax = fmax(emax, ev[j]);
     bool ok = emax > 0.0;
     for (int j = 0; j < m; ++j) ok = ok && (ev[j] > 1e-14 * emax);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) *info = ok ? 0 : 1;
+    if (e == 0 && (pass == 0 || !ok)) *info = ok ? 0 : 1;
     if (e >= m * m) return;
     const int j = e % m;
     Pq[e] = ok ? V[e] / sqrt(ev[j]) : 0.0;
@@ -259,6 +260,7 @@ __device__ __forceinline__ int low_idx(int i, int j) { return i * (i + 1) / 2 + 
 __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* __restrict__ G, int m,
                                                                  double* __restrict__ Rinv, int32_t* info, int pass) {
     __shared__ double sL[kCholN * (kCholN + 1) / 2];
+    __shared__ double colj[kCholN];   // copy of the current column: reads never alias the writes
     __shared__ double s_dmax;
     __shared__ int s_bad;
     const int tid = threadIdx.x;
@@ -275,6 +277,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* _
     }
     __syncthreads();
     const double dmax = s_dmax;
+    // right-looking Cholesky, one column per step
     for (int j = 0; j < m; ++j) {
         if (tid == 0) {
             double dj = sL[low_idx(j, j)];
@@ -285,33 +288,56 @@ __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* _
             sL[low_idx(j, j)] = sqrt(dj);
         }
         __syncthreads();
-        const double ljj = sL[low_idx(j, j)];
-        for (int i = j + 1 + tid; i < m; i += kCholThreads) sL[low_idx(i, j)] /= ljj;
+        const double inv = 1.0 / sL[low_idx(j, j)];
+        for (int i = j + 1 + tid; i < m; i += kCholThreads) {
+            const double v = sL[low_idx(i, j)] * inv;
+            sL[low_idx(i, j)] = v;
+            colj[i] = v;
+        }
         __syncthreads();
-        // trailing update A[i][l] -= L[i][j] L[l][j] for j < l <= i; S threads per row
+        // trailing update A[i][l] -= L[i][j] L[l][j], j < l <= i, S threads per row
         const int w = m - j - 1;
         if (w > 0) {
             const int S = max(1, kCholThreads / w);
             const int row = tid / S, sub = tid % S;
             if (row < w) {
                 const int i = j + 1 + row;
-                const double lij = sL[low_idx(i, j)];
-                for (int l = j + 1 + sub; l <= i; l += S) sL[low_idx(i, l)] -= lij * sL[low_idx(l, j)];
+                const double lij = colj[i];
+                double* Li = sL + low_idx(i, 0);
+                for (int l = j + 1 + sub; l <= i; l += S) Li[l] -= lij * colj[l];
             }
         }
         __syncthreads();
     }
     if (tid == 0 && (pass == 0 || s_bad)) *info = s_bad;
-    // column c of L^-1 = row c of Rinv: x_c = 1/L_cc, x_i = -(sum_{l=c}^{i-1} L_il x_l) / L_ii
-    for (int c = tid; c < m; c += kCholThreads) {
-        double* x = Rinv + (size_t)c * m;
-        for (int i = 0; i < c; ++i) x[i] = 0.0;
-        x[c] = 1.0 / sL[low_idx(c, c)];
-        for (int i = c + 1; i < m; ++i) {
+    // in-place inverse of L, last column first: with the trailing block already
+    // inverted, column j of L^-1 is -(1/L_jj) Linv[j+1:, j+1:] L[j+1:, j];
+    // each row's dot product is split over S lanes of one wave
+    for (int j = m - 1; j >= 0; --j) {
+        for (int i = j + 1 + tid; i < m; i += kCholThreads) colj[i] = sL[low_idx(i, j)];
+        __syncthreads();
+        const double djj = 1.0 / sL[low_idx(j, j)];
+        const int w = m - j - 1;
+        if (w > 0) {
+            int S = 64;
+            while (S > 1 && S * w > kCholThreads) S >>= 1;
+            const int row = tid / S, sub = tid % S;
             double acc = 0.0;
-            for (int l = c; l < i; ++l) acc += sL[low_idx(i, l)] * x[l];
-            x[i] = -acc / sL[low_idx(i, i)];
+            const int i = j + 1 + row;
+            if (row < w) {
+                const double* Li = sL + low_idx(i, 0);
+                for (int l = j + 1 + sub; l <= i; l += S) acc += Li[l] * colj[l];
+            }
+            for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (row < w && sub == 0) sL[low_idx(i, j)] = -djj * acc;
         }
+        __syncthreads();
+        if (tid == 0) sL[low_idx(j, j)] = djj;
+        __syncthreads();
+    }
+    for (int e = tid; e < m * m; e += kCholThreads) {
+        const int c = e / m, i = e % m;
+        Rinv[e] = (i >= c) ? sL[low_idx(i, c)] : 0.0;
     }
 }
 
@@ -509,13 +535,20 @@ extern "C" int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double*
         }
         return OTM_OK;
     }
-    if ((st = gemm_tn(Y, m, Y, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
-    hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, Gr, m);
-    if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
-    if ((st = jacobi(Gr, V, m, ev, ord, jws, s)) != OTM_OK) return st;
-    hipLaunchKernelGGL(orth_scale_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, V, ev, m, Pq, info);
-    if ((st = check_launch("orth_scale_kernel")) != OTM_OK) return st;
-    return gemm_nn(Y, m, Pq, m, Q, m, d, m, m, s);
+    // larger m: Q = Y (Y^T Y)^(-1/2), also applied twice
+    const double* src = Y;
+    for (int pass = 0; pass < 2; ++pass) {
+        double* dst = pass == 0 ? Q1 : Q;
+        if ((st = gemm_tn(src, m, src, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, Gr, m);
+        if ((st = check_launch("symmetrize_kernel")) != OTM_OK) return st;
+        if ((st = jacobi(Gr, V, m, ev, ord, jws, s)) != OTM_OK) return st;
+        hipLaunchKernelGGL(orth_scale_kernel, dim3((m * m + 255) / 256), dim3(256), 0, s, V, ev, m, Pq, info, pass);
+        if ((st = check_launch("orth_scale_kernel")) != OTM_OK) return st;
+        if ((st = gemm_nn(src, m, Pq, m, dst, m, d, m, m, s)) != OTM_OK) return st;
+        src = Q1;
+    }
+    return OTM_OK;
 }
 
 extern "C" size_t otm_unwhiten_workspace(int32_t d, int32_t k) {

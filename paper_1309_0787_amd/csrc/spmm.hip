@@ -159,13 +159,22 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
 }
 
 // out[c] = scale * sum_b part[b][c], fixed order, FP64 accumulation
-__global__ void colsum_finalize_kernel(const float* __restrict__ part, int nblocks, int k, double scale,
-                                       float* __restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= k) return;
+// One workgroup per column: strided FP64 partial sums, then a fixed-order LDS
+// tree, so the mean does not depend on scheduling.
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void colsum_finalize_kernel(const float* __restrict__ part, int nblocks,
+                                                                      int k, double scale, float* __restrict__ out) {
+    __shared__ double red[kFinThreads];
+    const int c = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * k + c];
-    out[c] = static_cast<float>(s * scale);
+    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += part[(size_t)b * k + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kFinThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = static_cast<float>(red[0] * scale);
 }
 
 template <int VPL, class TW, class TY>
@@ -382,7 +391,7 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
     }
     if (st != OTM_OK) return st;
     if (ybar) {
-        hipLaunchKernelGGL(colsum_finalize_kernel, dim3((k + 127) / 128), dim3(128), 0, s, part, p.nblocks, k,
+        hipLaunchKernelGGL(colsum_finalize_kernel, dim3(k), dim3(kFinThreads), 0, s, part, p.nblocks, k,
                            1.0 / C->n_rows, ybar);
         return check_launch("colsum_finalize_kernel");
     }

@@ -77,7 +77,7 @@ def test_whitener_sampled_graph():
 
 @pytest.mark.parametrize("normalize", [False, True])
 def test_power_sketch_chain(normalize):
-    """GPU sketch (eigen-based orthonormal bases) and oracle sketch (QR bases)
+    """GPU sketch (Cholesky-QR bases) and oracle sketch (Householder QR bases)
     span the same spaces, so the whiteners agree after the sign rule."""
     if normalize:
         inst = synth.lda(d=1500, k=6, alpha0=1.0, beta=0.1, n_docs=3000, mean_len=50.0, seed=3)
@@ -90,14 +90,38 @@ def test_power_sketch_chain(normalize):
     W, ev, _ = otm.whitener(Og, Qg, k)
     torch.cuda.synchronize()
     Qh = host(Qg)
-    # Y (Y^T Y)^(-1/2) is orthonormal to about eps * cond(Y^T Y) (the Jacobi
-    # eigensolver stops at off-diagonals below 1e-15 ||Y^T Y||_F); only span(Q)
-    # matters downstream, which the whitener comparison below checks
+    # orthonormal to about eps * cond(Y) after the second Cholesky-QR pass; only
+    # span(Q) matters downstream, which the whitener comparison below checks
     np.testing.assert_allclose(Qh.T @ Qh, np.eye(2 * k), atol=1e-10)
     Qo, Oo = oracle.power_sketch(C, S, a0, normalize, 3)
     Wref, evref = oracle.whitener_rsvd(Oo, Qo, k)
     assert rel(host(W), Wref) < 1e-8
     np.testing.assert_allclose(host(ev), evref, rtol=1e-9)
+
+
+@pytest.mark.parametrize("d,m", [(50, 1), (300, 7), (1000, 64), (5000, 200), (2000, 256)])
+def test_orthonormalize(d, m):
+    """m <= 200: Cholesky QR gives the QR factor whose R has a positive
+    diagonal, which is unique, so it must equal NumPy's QR after that sign fix.
+    m > 200: Y (Y^T Y)^(-1/2); orthonormal with the same span."""
+    gen = np.random.default_rng(d + m)
+    Y = gen.standard_normal((d, m)) @ np.diag(np.logspace(0, 3, m))     # cond(Y) = 1e3
+    Q = host(otm.orthonormalize(to_dev(Y, torch.float64)))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(m), atol=1e-12)
+    if m <= 200:
+        Qr, R = np.linalg.qr(Y)
+        Qr = Qr * np.sign(np.diag(R))
+        assert rel(Q, Qr) < 1e-11
+    else:
+        assert rel(Q @ (Q.T @ Y), Y) < 1e-12
+
+
+def test_orthonormalize_rank_deficient():
+    gen = np.random.default_rng(1)
+    Y = gen.standard_normal((400, 10))
+    Y[:, 7] = Y[:, 2] - 0.5 * Y[:, 4]
+    with pytest.raises(otm.OtmError):
+        otm.orthonormalize(to_dev(Y, torch.float64))
 
 
 def test_whitener_not_psd():
