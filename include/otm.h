@@ -193,6 +193,99 @@ int otm_sgd_run(const otm_sgd_params* p, int32_t n, const void* YA, const void* 
                 int32_t restarts, int64_t start_step, int64_t end_step, float* Phi,
                 float* Phi_comp, float* snapshots, int32_t* nonfinite, otm_stream stream);
 
+/* ---- restart score (Section 3.2 objective; selection among restarts) -----
+ * score_r = sum_ij (phi_i^T phi_j)^3 - 2 sum_i T(phi_i, phi_i, phi_i)
+ *         = ||sum_i phi_i^(x3) - T||_F^2 - ||T||_F^2
+ * for each of `restarts` factor matrices Phi + r*k*k (k x k FP32, phi_i
+ * contiguous), with T the whitened, Dirichlet-corrected tensor of the n rows
+ * of YA/YB/YC (the tensor the update of Lemma "update" descends on, with the
+ * global means ybar).  The lowest score is the lowest residual.  One pass over
+ * the rows, the same contractions as a step, no update; FP32 products summed
+ * in FP64 across batches.  y_dtype must be OTM_F32; p->passes is ignored.
+ * score: restarts FP64 (device).  ws: otm_sgd_score_workspace(restarts). */
+size_t otm_sgd_score_workspace(int32_t restarts);
+int otm_sgd_score(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB, const void* YC,
+                  const float* ybar, const float* Phi, int32_t restarts, double* score,
+                  void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- batched STGD: many decompositions with restarts in one persistent
+ * launch (the per-problem computation is otm_sgd_run with a scoring pass) ---
+ * A problem is one decomposition: whitened views of n rows, k components,
+ * `restarts` runs from the initial factors Phi0 + r*k*k, results Phi + r*k*k,
+ * scores score[r] as in otm_sgd_score of the final factors.  perms: NULL
+ * (rows in order) or, per run r, passes x n int32 at perms + r*perm_stride.
+ * Every pointer is device memory owned by the caller. */
+typedef struct {
+    const void* YA;
+    const void* YB;
+    const void* YC;
+    const float* ybar;        /* 3 x k */
+    const int32_t* perms;
+    int64_t perm_stride;
+    const float* Phi0;        /* restarts x k x k, read only */
+    float* Phi;               /* restarts x k x k, written */
+    double* score;            /* restarts, written */
+    int32_t n, k, ldy;
+    int32_t pad_;
+    double alpha0;
+} otm_problem;
+
+/* Host-only planning (no GPU call): one job per (problem, restart).  Each
+ * job's kernel variant (padded k, tile layout, view staging) comes from the
+ * tuning cache file (NULL or a missing entry: the default layout); jobs are
+ * grouped by variant, longest first inside a group (estimated from the steps
+ * and the tuned cost per step).  The shared settings (batch, passes,
+ * y_dtype = OTM_F32, compensated, theta, beta0, beta_tau) come from p; p->k,
+ * p->ldy and p->alpha0 are ignored.  best: device int32 per problem, the
+ * lowest-score restart (ties to the lower index), written by the run.
+ * nonfinite: NULL or device int32, cleared at the start of each run and set
+ * as in otm_sgd_run.  *plan receives a host object (free it with
+ * otm_plan_free); its device image (otm_plan_image, otm_plan_size bytes) is
+ * plain data that the caller copies to device memory for the runs. */
+typedef struct otm_plan_s* otm_plan;
+int otm_sgd_batched_plan(const otm_problem* problems, int32_t n_problems, int32_t restarts,
+                         const otm_sgd_params* p, const char* tune_cache, int32_t* best,
+                         int32_t* nonfinite, otm_plan* plan);
+size_t otm_plan_size(otm_plan plan);
+const void* otm_plan_image(otm_plan plan);
+int32_t otm_plan_groups(otm_plan plan);   /* kernel variants the plan uses */
+/* Variant of group g (in launch order): padded k, tile layout (0 or 1), views
+ * (1 = one aliased view, 3 = three views) and its number of jobs. */
+int otm_plan_group_info(otm_plan plan, int32_t group, int32_t* kp, int32_t* layout, int32_t* views,
+                        int32_t* jobs);
+int otm_plan_free(otm_plan plan);
+
+/* Runs a plan whose image is at `image` (device memory): a kernel clears the
+ * queue counters and the nonfinite flag; one persistent kernel per variant
+ * group runs on library-owned branch streams forked from `stream` (all
+ * concurrent; each group's workgroups, sized by its share of the estimated
+ * work, pull jobs until the group's queue is empty); the branches join back
+ * into `stream`, and a last kernel writes best.  The image must stay
+ * unchanged while the run is in flight.  ws: otm_sgd_batched_workspace(plan)
+ * bytes.  No device allocation, no memset node: the call can be captured into
+ * a graph (otm_sgd_batched_graph).  Runs on one device must not be issued
+ * from several host threads at once (they share the branch streams). */
+size_t otm_sgd_batched_workspace(otm_plan plan);
+int otm_sgd_batched(otm_plan plan, const void* image, void* ws, size_t ws_bytes, otm_stream stream);
+
+/* The same launch sequence captured into a graph on `stream` (not the null
+ * stream) and instantiated; replays compute the same results (every output
+ * is overwritten, Phi0 is only read).  otm_graph_launch replays it on a
+ * stream; otm_graph_destroy frees it. */
+typedef struct otm_graph_s* otm_graph;
+int otm_sgd_batched_graph(otm_plan plan, const void* image, void* ws, size_t ws_bytes, otm_stream stream,
+                          otm_graph* graph);
+int otm_graph_launch(otm_graph graph, otm_stream stream);
+int otm_graph_destroy(otm_graph graph);
+
+/* Tile-layout autotuner for the batched kernel: for each padded k of ks and
+ * each view layout (one aliased view, three views) it times the kernel
+ * variants on a full device of synthetic probe jobs (batch rows of random
+ * whitened data, one pass), and records the fastest in the text file
+ * cache_path (merged with its existing entries).  Allocates and frees its own
+ * probe buffers (setup time, not for capture); synchronises the stream. */
+int otm_sgd_autotune(const int32_t* ks, int32_t n_k, int32_t batch, const char* cache_path, otm_stream stream);
+
 /* ---- a6: post-processing (Section 3.3, Lemma "postprocessing") -----------
  * lambda_i = kappa ||phi_i||^3, u_i = phi_i / ||phi_i||,
  * mu_i = lambda_i (W^T)^+ u_i with (W^T)^+ = W (W^T W)^(-1), negatives

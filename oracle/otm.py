@@ -18,7 +18,7 @@ __all__ = [
     "NotPSDError", "as_sparse", "row_weights", "dirichlet_coefficients", "first_moment",
     "m2_apply", "power_sketch", "whitener_rsvd", "canonical_signs", "whiten", "sgd_step", "sgd_direction",
     "sgd_run", "beta_schedule", "steps_per_pass", "whitened_tensor", "residual",
-    "unwhiten_topics", "recover_pi", "eigen_from_factors",
+    "unwhiten_topics", "recover_pi", "eigen_from_factors", "restart_score", "best_restart", "sgd_batched",
 ]
 
 
@@ -282,6 +282,40 @@ def residual(T: np.ndarray, Phi: np.ndarray) -> float:
     cross = float(np.einsum("ijl,ia,ja,la->", T, Phi, Phi, Phi))
     tt = float(np.sum(T * T))
     return (self_term - 2.0 * cross + tt) / tt
+
+
+def restart_score(T: np.ndarray, Phi: np.ndarray) -> float:
+    """Score of a restart's final factors: ||sum_i phi_i^(x3) - T||_F^2 - ||T||_F^2
+    = sum_ij (phi_i^T phi_j)^3 - 2 sum_i T(phi_i, phi_i, phi_i).  READING (the
+    paper leaves the choice among restarts open): restarts are ranked by the
+    residual of the objective of Section 3.2; ||T||^2 is the same for every
+    restart of a problem, so it is left out."""
+    G = Phi.T @ Phi
+    return float(np.sum(G ** 3)) - 2.0 * float(np.einsum("ijl,ia,ja,la->", T, Phi, Phi, Phi))
+
+
+def best_restart(scores) -> int:
+    """Index of the lowest score; ties go to the lower index."""
+    return int(np.argmin(np.asarray(scores)))
+
+
+def sgd_batched(problems, batch: int, beta0: float, tau: float, theta: float = 1.0):
+    """Independent decompositions, each with several restarts: every restart
+    is an online run (sgd_run) of its problem, scored by restart_score; the
+    best restart is the lowest score.  problems: dicts with YA, YB, YC, ybar
+    (3 x k), alpha0, Phi0 (list of k x k, phi_i as columns) and perms (list of
+    passes x n, one per restart).  Returns, per problem, (list of final Phi,
+    list of scores, best index)."""
+    out = []
+    for P in problems:
+        T = whitened_tensor(P["YA"], P["YB"], P["YC"], P["ybar"], P["alpha0"])
+        phis, scores = [], []
+        for Phi0, perms in zip(P["Phi0"], P["perms"]):
+            Phi = sgd_run(P["YA"], P["YB"], P["YC"], P["ybar"], Phi0, perms, batch, beta0, tau, P["alpha0"], theta)
+            phis.append(Phi)
+            scores.append(restart_score(T, Phi))
+        out.append((phis, scores, best_restart(scores)))
+    return out
 
 
 # ----------------------------------------------------------------------------

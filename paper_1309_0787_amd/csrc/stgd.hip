@@ -1,664 +1,14 @@
-// Stochastic tensor gradient descent on the implicit whitened third moment
-// (Section 3.2, Lemma "update"), in the stacked matrix form of Section 4.3:
-//
-//   PA = YA Phi, PB = YB Phi                       (batch x k, matrix cores)
-//   mA = Phi^T ybarA, mB = Phi^T ybarB             (k, vector ALU)
-//   H  = PA * PB,  s = column sums of H            (wave shuffles)
-//   Q  = a H - b PA diag(mB) - b diag(mA) PB
-//   D  = YC^T Q / B + ybarC (c mA*mB - b s / B)^T  (matrix cores)
-//   G  = Phi^T Phi,  O = Phi (G * G)               (matrix cores)
-//   Phi <- Phi + beta (D - kappa O)                 (compensated FP32)
-//
-// One workgroup of 8 waves runs one whole online run (all steps), keeping the
-// FP32 master copy of Phi (and its Kahan compensation) in registers.  The
-// tensor is never formed.  Wave (wr, wc), wr in 0..3, wc in 0..1, owns the
-// 16x16 output tiles (mt, nt) with mt = wr mod 4 and nt = wc mod 2 of every
-// product, so the update of a Phi tile needs only the O and D tiles the same
-// wave computed.  LDS holds operand copies of Phi (phi_i-major, plus an
-// a-major copy for BF16 fragments), a buffer that carries G*G and then Q from
-// the accumulator layout to the operand layout, the mini-batch of whitened
-// rows, and small vectors.
-//
-// Batch staging (NSTAGE = 1 for one shared view, 3 for three views): the rows
-// of step t+1 are fetched into registers while step t computes (indices during
-// the Phi^T Phi and Phi (G*G) products, data during the rest) and written to
-// LDS row-major at the start of step t+1, so the products never wait on
-// global memory.  NSTAGE = 0 (shapes whose batch does not fit in LDS) reads
-// the rows from global memory inside the products.
-//
-// Four workgroup barriers per step: after G*G, after O (the buffer then
-// takes Q), after Q, after the update.  The batch is padded to 128 rows in
-// every product, so every tile loop has a compile-time trip count.
-#include <cmath>
-
-#include "otm_internal.h"
+// Entry points of the single-problem STGD (the kernel body is in stgd_kernel.h).
+#include "stgd_kernel.h"
 
 namespace otm {
 namespace {
 
-// ---------------------------------------------------------------------------
-// Matrix-core flavours.  Lane l of a 16x16xKI instruction supplies
-//   A[l % 16][EPL*(l/16) + e] and B[EPL*(l/16) + e][l % 16], e < EPL,
-// and receives C[4*(l/16) + r][l % 16], r < 4.
-// ---------------------------------------------------------------------------
-struct MmaF32 {
-    using Y = float;
-    using Op = float;
-    using Frag = float;
-    using Chunk = f32x4;                      // 16-byte row piece of the batch
-    static constexpr int KI = 4;
-    static constexpr int EPL = 1;
-    static constexpr int SPAD = 4;            // LDS row padding (elements)
-    static constexpr int CH = 4;              // elements per chunk
-    static constexpr bool kPhiT = false;
-    __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static Frag lds(const Op* p) { return *p; }
-    __device__ static Op to_op(float x) { return x; }
-    __device__ static float op_to_f(Op x) { return x; }
-    __device__ static Frag zero_frag() { return 0.0f; }
-    // fragment of EPL consecutive row elements a0.. (masked at k)
-    __device__ static Frag yrow(const Y* row, int a0, int k) {
-        return (row != nullptr && a0 < k) ? row[a0] : 0.0f;
-    }
-    __device__ static Chunk load_chunk(const Y* p, int valid) {
-        Chunk v = *reinterpret_cast<const Chunk*>(p);
-#pragma unroll
-        for (int e = 0; e < CH; ++e)
-            if (e >= valid) v[e] = 0.0f;
-        return v;
-    }
-    __device__ static Chunk zero_chunk() { return Chunk{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static void store4(Op* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
-    __device__ static f32x4 load4(const Op* p) { return *reinterpret_cast<const f32x4*>(p); }
-};
-
-struct MmaBF16 {
-    using Y = __bf16;
-    using Op = __bf16;
-    using Frag = bf16x8;
-    using Chunk = bf16x8;
-    static constexpr int KI = 32;
-    static constexpr int EPL = 8;
-    static constexpr int SPAD = 8;
-    static constexpr int CH = 8;
-    static constexpr bool kPhiT = true;
-    __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    }
-    __device__ static Frag lds(const Op* p) { return *reinterpret_cast<const bf16x8*>(p); }
-    __device__ static Op to_op(float x) { return f32_to_bf16(x); }
-    __device__ static float op_to_f(Op x) { return bf16_to_f32(x); }
-    __device__ static Frag zero_frag() {
-        bf16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = f32_to_bf16(0.0f);
-        return v;
-    }
-    __device__ static Frag yrow(const Y* row, int a0, int k) {
-        if (row != nullptr && a0 < k) {
-            // ldy % 8 == 0 and a0 % 8 == 0: the 16-byte load stays inside the row
-            bf16x8 v = *reinterpret_cast<const bf16x8*>(row + a0);
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (a0 + e >= k) v[e] = f32_to_bf16(0.0f);
-            return v;
-        }
-        return zero_frag();
-    }
-    __device__ static Chunk load_chunk(const Y* p, int valid) {
-        Chunk v = *reinterpret_cast<const Chunk*>(p);
-#pragma unroll
-        for (int e = 0; e < CH; ++e)
-            if (e >= valid) v[e] = f32_to_bf16(0.0f);
-        return v;
-    }
-    __device__ static Chunk zero_chunk() { return zero_frag(); }
-    __device__ static void store4(Op* p, f32x4 v) {
-        bf16x4 o;
-        o[0] = f32_to_bf16(v[0]);
-        o[1] = f32_to_bf16(v[1]);
-        o[2] = f32_to_bf16(v[2]);
-        o[3] = f32_to_bf16(v[3]);
-        *reinterpret_cast<bf16x4*>(p) = o;
-    }
-};
-
-struct SgdArgs {
-    const void* YA;
-    const void* YB;
-    const void* YC;
-    const float* ybar;
-    const int32_t* perms;
-    int64_t perm_stride;
-    float* Phi;
-    float* Phi_comp;
-    float* snapshots;
-    int32_t* nonfinite;
-    int32_t n, k, batch, passes, ldy, compensated;
-    int32_t start_step, end_step, spp;
-    float a, b, c, kappa;
-    float beta0, inv_tau;
-};
-
-constexpr int kWaves = 8;
-constexpr int kThreads = 64 * kWaves;
-constexpr int MB = kMaxBatch;           // batch rows padded to 128 in every product
-constexpr int NTM = MB / 16;            // batch tiles
-constexpr int kTR = NTM / 4;            // batch tile rows per wave
-
-template <class M, int KP, int NSTAGE>
-struct SgdSmem {
-    using Op = typename M::Op;
-    using Y = typename M::Y;
-    static constexpr int SP = KP + M::SPAD;        // Phi rows
-    static constexpr int SB = MB + M::SPAD;        // exchange buffer rows (t or j)
-    static constexpr int SY = KP + M::SPAD;        // staged batch rows
-    static constexpr bool kStageCT = (NSTAGE == 0) && M::kPhiT;   // BF16 fallback: YC batch a-major
-    alignas(16) Op phi[KP * SP];
-    alignas(16) Op phiT[M::kPhiT ? KP * SP : 1];
-    alignas(16) Op buf[KP * SB];
-    alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * MB * SY : 1];
-    alignas(16) Op yct[kStageCT ? KP * SB : 1];
-    alignas(16) int32_t idx[MB];
-    alignas(16) float ybar[3 * KP];
-    alignas(16) float m[2 * KP];
-    alignas(16) float s[4 * KP];
-};
-
-template <class M, int KP, int NSTAGE>
-constexpr size_t smem_bytes() { return sizeof(SgdSmem<M, KP, NSTAGE>); }
-
 template <class M, int KP, int NSTAGE>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
-    using Op = typename M::Op;
-    using Y = typename M::Y;
-    using SM = SgdSmem<M, KP, NSTAGE>;
-    constexpr int NTK = KP / 16;
-    constexpr int TC = (NTK + 1) / 2;              // tile columns per wave
-    constexpr int TRK = (NTK + 3) / 4;             // tile rows per wave in the k x k products
-    constexpr int SP = SM::SP, SB = SM::SB, SY = SM::SY;
-    constexpr int cpr = KP / M::CH;                // 16-byte chunks per batch row
-    constexpr int NCH = (MB * cpr + kThreads - 1) / kThreads;   // chunks per thread when staging
-    constexpr int UNR = (M::KI >= 32) ? 4 : 2;     // unroll of the contraction loops
-    __shared__ __attribute__((aligned(16))) SM sm;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    // wave index in a scalar register: every tile guard below is a scalar branch
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = (w >> 1) & 3, wc = w & 1;
-    const int l16 = lane & 15, q = lane >> 4;
-
-    const int k = g.k;
-    const int n = g.n, ldy = g.ldy, B = g.batch;
-    const int r_id = blockIdx.x;
-    float* Phi = g.Phi + (size_t)r_id * k * k;
-    float* Comp = g.Phi_comp ? g.Phi_comp + (size_t)r_id * k * k : nullptr;
-    float* Snap = g.snapshots ? g.snapshots + (size_t)r_id * g.passes * k * k : nullptr;
-    const int32_t* perms = g.perms ? g.perms + (size_t)r_id * g.perm_stride : nullptr;
-    const Y* Yv[3] = {static_cast<const Y*>(g.YA), static_cast<const Y*>(g.YB), static_cast<const Y*>(g.YC)};
-    bool bad = false;
-    const float cmask = g.compensated ? 1.0f : 0.0f;
-    // mA = Phi^T ybarA and mB = Phi^T ybarB ride along in Phi^T Phi when two
-    // padding rows are free: the phi_i-major operand holds ybarA, ybarB as
-    // "components" k and k+1 (never updated, zero in the a-major copy), so
-    // G[i][k] = mA[i] and G[i][k+1] = mB[i].
-    const bool mfold = (k + 2 <= KP);
-
-    // ---- master copy of Phi in registers: tile (mt, nt) holds a = row, i = column
-    f32x4 phi[TRK][TC], comp[TRK][TC];
-#pragma unroll
-    for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < TC; ++tj) {
-            const int mt = wr + 4 * ti, nt = wc + 2 * tj;
-            f32x4 v = {0.f, 0.f, 0.f, 0.f}, cv = {0.f, 0.f, 0.f, 0.f};
-            if (mt < NTK && nt < NTK) {
-                const int i = nt * 16 + l16;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int a = mt * 16 + 4 * q + r;
-                    if (a < k && i < k) {
-                        v[r] = Phi[(size_t)i * k + a];
-                        if (Comp && g.compensated) cv[r] = Comp[(size_t)i * k + a];
-                    } else if (mfold && a < k && (i == k || i == k + 1)) {
-                        v[r] = g.ybar[(i - k) * k + a];
-                    }
-                }
-                M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
-                if constexpr (M::kPhiT) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(i < k ? v[r] : 0.0f);
-                }
-            }
-            phi[ti][tj] = v;
-            comp[ti][tj] = cv;
-        }
-    for (int e = tid; e < 3 * KP; e += kThreads) {
-        const int v = e / KP, a = e % KP;
-        sm.ybar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
-    }
-    // per-column factor of the update: 1 for a live component, 0 for padding
-    float live[TC];
-#pragma unroll
-    for (int tj = 0; tj < TC; ++tj) live[tj] = ((wc + 2 * tj) * 16 + l16 < k) ? 1.0f : 0.0f;
-
-    // ---- batch prefetch state (NSTAGE > 0)
-    int32_t pidx[NCH];
-    typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
-    auto issue_index = [&](int t) {
-        if constexpr (NSTAGE > 0) {
-            const bool live_step = t < g.end_step;
-            const int pass = live_step ? t / g.spp : 0;
-            const int row0 = live_step ? (t - pass * g.spp) * B : 0;
-            const int nb = live_step ? min(B, n - row0) : 0;
-            const int32_t* pp = perms ? perms + (size_t)pass * n + row0 : nullptr;
-#pragma unroll
-            for (int j = 0; j < NCH; ++j) {
-                const int c = tid + j * kThreads;
-                const int tr = c / cpr;
-                int32_t r = -1;
-                if (c < MB * cpr && tr < nb) {
-                    r = pp ? pp[tr] : row0 + tr;
-                    if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
-                        r = 0;
-                        bad = true;
-                    }
-                }
-                pidx[j] = r;
-            }
-        }
-    };
-    auto issue_data = [&]() {
-        if constexpr (NSTAGE > 0) {
-#pragma unroll
-            for (int j = 0; j < NCH; ++j) {
-                const int c = tid + j * kThreads;
-                const int a0 = (c % cpr) * M::CH;
-#pragma unroll
-                for (int v = 0; v < NSTAGE; ++v)
-                    pbuf[v][j] = (pidx[j] >= 0 && a0 < k)
-                                     ? M::load_chunk(Yv[v] + (size_t)pidx[j] * ldy + a0, k - a0)
-                                     : M::zero_chunk();
-            }
-        }
-    };
-    auto commit = [&]() {
-        if constexpr (NSTAGE > 0) {
-#pragma unroll
-            for (int j = 0; j < NCH; ++j) {
-                const int c = tid + j * kThreads;
-                if (c < MB * cpr) {
-                    const int tr = c / cpr, a0 = (c % cpr) * M::CH;
-#pragma unroll
-                    for (int v = 0; v < NSTAGE; ++v)
-                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * MB + tr) * SY + a0]) = pbuf[v][j];
-                }
-            }
-        }
-    };
-    issue_index(g.start_step);
-    issue_data();
-    __syncthreads();
-
-    for (int t = g.start_step; t < g.end_step; ++t) {
-        const int pass = t / g.spp;
-        const int s = t - pass * g.spp;
-        const int row0 = s * B;
-        const int nb = min(B, n - row0);
-        const float beta = g.beta0 / (1.0f + static_cast<float>(t) * g.inv_tau);
-
-        // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
-        commit();
-        issue_index(t + 1);
-        if constexpr (NSTAGE == 0) {
-            if (tid < nb) {
-                int32_t r = perms ? perms[(size_t)pass * n + row0 + tid] : row0 + tid;
-                if (r < 0 || r >= n) {
-                    r = 0;
-                    bad = true;
-                }
-                sm.idx[tid] = r;
-            }
-        }
-        if (!mfold) {
-            // mA, mB on the vector ALU: thread (view v, column i, half h) sums half a dot product
-            const int v = tid >> 8, rem = tid & 255, i = rem >> 1, h = rem & 1;
-            float acc = 0.f;
-            if (i < KP) {
-                constexpr int half = KP >> 1;
-                const Op* prow = &sm.phi[i * SP + h * half];
-                const float* yb = &sm.ybar[v * KP + h * half];
-#pragma unroll
-                for (int a = 0; a < half; a += 8) {
-                    float x[8];
-                    if constexpr (M::EPL == 8) {
-                        const bf16x8 pv = *reinterpret_cast<const bf16x8*>(prow + a);
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) x[e] = M::op_to_f(pv[e]);
-                    } else {
-                        const f32x4 p0 = M::load4(prow + a), p1 = M::load4(prow + a + 4);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) { x[e] = p0[e]; x[e + 4] = p1[e]; }
-                    }
-                    const f32x4 y0 = *reinterpret_cast<const f32x4*>(yb + a);
-                    const f32x4 y1 = *reinterpret_cast<const f32x4*>(yb + a + 4);
-                    acc += x[0] * y0[0] + x[1] * y0[1] + x[2] * y0[2] + x[3] * y0[3] +
-                           x[4] * y1[0] + x[5] * y1[1] + x[6] * y1[2] + x[7] * y1[3];
-                }
-            }
-            acc += __shfl_xor(acc, 1);
-            if (h == 0 && i < KP) sm.m[v * KP + i] = acc;
-        }
-        {
-            f32x4 acc[TRK][TC];
-#pragma unroll
-            for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll UNR
-            for (int k0 = 0; k0 < KP; k0 += M::KI) {
-                typename M::Frag fa[TRK], fb[TC];
-#pragma unroll
-                for (int ti = 0; ti < TRK; ++ti) {
-                    const int mt = wr + 4 * ti;
-                    fa[ti] = (mt < NTK) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
-                }
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    const int nt = wc + 2 * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
-                }
-#pragma unroll
-                for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < TC; ++tj)
-                        if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
-                            acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
-            }
-            // G*G into the exchange buffer, column-major: buf[i*SB + j] = G[j][i]^2;
-            // the columns k, k+1 of G give mA, mB when folded
-#pragma unroll
-            for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    const int mt = wr + 4 * ti, nt = wc + 2 * tj;
-                    if (mt < NTK && nt < NTK) {
-                        const int i = nt * 16 + l16;
-                        const f32x4 gv = acc[ti][tj];
-                        M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], gv * gv);
-                        if (mfold && (i == k || i == k + 1))
-                            *reinterpret_cast<f32x4*>(&sm.m[(i - k) * KP + mt * 16 + 4 * q]) = gv;
-                    }
-                }
-        }
-        __syncthreads();
-
-        // ================= phase 2: O = Phi (G*G), kept in registers until the update
-        f32x4 oacc[TRK][TC];
-#pragma unroll
-        for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < TC; ++tj) oacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll UNR
-        for (int k0 = 0; k0 < KP; k0 += M::KI) {
-            typename M::Frag fa[TRK], fb[TC];
-#pragma unroll
-            for (int ti = 0; ti < TRK; ++ti) {
-                const int mt = wr + 4 * ti;
-                const int a = mt * 16 + l16;
-                if (mt < NTK) {
-                    if constexpr (M::kPhiT) fa[ti] = M::lds(&sm.phiT[a * SP + k0 + q * M::EPL]);
-                    else fa[ti] = (k0 + q < k) ? sm.phi[(k0 + q) * SP + a] : 0.0f;   // a-major view, live columns
-                } else {
-                    fa[ti] = M::zero_frag();
-                }
-            }
-#pragma unroll
-            for (int tj = 0; tj < TC; ++tj) {
-                const int nt = wc + 2 * tj;
-                fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
-            }
-#pragma unroll
-            for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj)
-                    if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
-                        oacc[ti][tj] = M::mma(fa[ti], fb[tj], oacc[ti][tj]);
-        }
-        __syncthreads();   // every read of G*G is done: the buffer takes Q next
-
-        // rows of step t+1 start their trip from global memory now
-        issue_data();
-
-        // ================= phase 3: PA, PB one tile row at a time -> Q into the
-        // exchange buffer (buf[i*SB + t] = Q[t][i]) and column sums of H
-        {
-            // per column: Q = al*xa*xb - bmB*xa - bmA*xb with the padding mask folded in
-            float colsum[TC];
-            float al[TC], bmA[TC], bmB[TC];
-#pragma unroll
-            for (int tj = 0; tj < TC; ++tj) {
-                colsum[tj] = 0.f;
-                const int i = (wc + 2 * tj) * 16 + l16;
-                const float mA = (wc + 2 * tj < NTK) ? sm.m[i] : 0.f;
-                const float mB = (wc + 2 * tj < NTK) ? sm.m[KP + i] : 0.f;
-                al[tj] = g.a * live[tj];
-                bmA[tj] = g.b * live[tj] * mA;
-                bmB[tj] = g.b * live[tj] * mB;
-            }
-#pragma unroll
-            for (int ti = 0; ti < kTR; ++ti) {
-                const int mt = wr + 4 * ti;
-                const int tr = mt * 16 + l16;
-                const Y* rowA = nullptr;
-                const Y* rowB = nullptr;
-                if constexpr (NSTAGE == 0) {
-                    const bool ok = tr < nb;
-                    rowA = ok ? Yv[0] + (size_t)sm.idx[tr] * ldy : nullptr;
-                    rowB = ok ? Yv[1] + (size_t)sm.idx[tr] * ldy : nullptr;
-                }
-                const Y* sA = &sm.ybatch[tr * SY];
-                const Y* sB = &sm.ybatch[((NSTAGE == 3 ? 1 : 0) * MB + tr) * SY];
-                f32x4 pa[TC], pb[TC];
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    pa[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    pb[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-#pragma unroll UNR
-                for (int k0 = 0; k0 < KP; k0 += M::KI) {
-                    typename M::Frag fa, fbv;
-                    if constexpr (NSTAGE == 0) {
-                        fa = M::yrow(rowA, k0 + q * M::EPL, k);
-                        fbv = M::yrow(rowB, k0 + q * M::EPL, k);
-                    } else {
-                        fa = M::lds(sA + k0 + q * M::EPL);
-                        if constexpr (NSTAGE == 3) fbv = M::lds(sB + k0 + q * M::EPL);
-                    }
-#pragma unroll
-                    for (int tj = 0; tj < TC; ++tj) {
-                        const int nt = wc + 2 * tj;
-                        if (nt < NTK) {
-                            const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
-                            pa[tj] = M::mma(fa, fphi, pa[tj]);
-                            if constexpr (NSTAGE != 1) pb[tj] = M::mma(fbv, fphi, pb[tj]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    const int nt = wc + 2 * tj;
-                    if (nt >= NTK) continue;
-                    const int i = nt * 16 + l16;
-                    f32x4 qv;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float xa = pa[tj][r];
-                        if constexpr (NSTAGE == 1) {   // one view: xb = xa
-                            colsum[tj] = fmaf(xa, xa, colsum[tj]);
-                            qv[r] = xa * fmaf(al[tj], xa, -(bmA[tj] + bmB[tj]));
-                        } else {
-                            const float xb = pb[tj][r];
-                            colsum[tj] = fmaf(xa, xb, colsum[tj]);
-                            qv[r] = fmaf(xa, fmaf(al[tj], xb, -bmB[tj]), -bmA[tj] * xb);
-                        }
-                    }
-                    M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], qv);
-                }
-            }
-#pragma unroll
-            for (int tj = 0; tj < TC; ++tj) {
-                const int nt = wc + 2 * tj;
-                if (nt >= NTK) continue;
-                colsum[tj] += __shfl_xor(colsum[tj], 16);
-                colsum[tj] += __shfl_xor(colsum[tj], 32);
-                if (q == 0) sm.s[wr * KP + nt * 16 + l16] = colsum[tj];
-            }
-        }
-        if constexpr (SM::kStageCT) {
-            // YC batch into LDS, a-major: yct[a*SB + t] (zero outside the batch and k)
-            for (int e = tid; e < MB * KP; e += kThreads) {
-                const int tr = e / KP, a = e % KP;
-                const Y v = (tr < nb && a < k) ? Yv[2][(size_t)sm.idx[tr] * ldy + a] : M::to_op(0.0f);
-                sm.yct[a * SB + tr] = v;
-            }
-        }
-        __syncthreads();
-
-        // ================= phase 4: D = YC^T Q (+ rank one), update Phi
-        {
-            constexpr int vc = (NSTAGE == 3) ? 2 : 0;
-            f32x4 dacc[TRK][TC];
-#pragma unroll
-            for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) dacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll UNR
-            for (int k0 = 0; k0 < MB; k0 += M::KI) {
-                typename M::Frag fa[TRK], fb[TC];
-#pragma unroll
-                for (int ti = 0; ti < TRK; ++ti) {
-                    const int mt = wr + 4 * ti;
-                    const int a = mt * 16 + l16;
-                    if (mt >= NTK) {
-                        fa[ti] = M::zero_frag();
-                    } else if constexpr (NSTAGE > 0) {
-                        // EPL rows t = k0 + EPL*q + e of column a of the staged batch
-                        if constexpr (M::EPL == 1) {
-                            fa[ti] = sm.ybatch[(vc * MB + k0 + q) * SY + a];
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < M::EPL; ++e)
-                                fa[ti][e] = sm.ybatch[(vc * MB + k0 + q * M::EPL + e) * SY + a];
-                        }
-                    } else if constexpr (SM::kStageCT) {
-                        fa[ti] = M::lds(&sm.yct[a * SB + k0 + q * M::EPL]);
-                    } else {
-                        const int tr = k0 + q;
-                        fa[ti] = (a < k && tr < nb) ? Yv[2][(size_t)sm.idx[tr] * ldy + a] : 0.0f;
-                    }
-                }
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    const int nt = wc + 2 * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
-                }
-#pragma unroll
-                for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < TC; ++tj)
-                        if (wr + 4 * ti < NTK && wc + 2 * tj < NTK)
-                            dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
-            }
-            const float invB = 1.0f / static_cast<float>(nb);
-#pragma unroll
-            for (int tj = 0; tj < TC; ++tj) {
-                const int nt = wc + 2 * tj;
-                if (nt >= NTK) continue;
-                const int i = nt * 16 + l16;
-                const float ssum = sm.s[i] + sm.s[KP + i] + sm.s[2 * KP + i] + sm.s[3 * KP + i];
-                const float rv = g.c * sm.m[i] * sm.m[KP + i] - g.b * ssum * invB;
-                // delta = beta*live*(dacc/B + ybarC*rv - kappa*O), folded per column
-                const float bl = beta * live[tj];
-                const float f1 = bl * invB, f2 = bl * rv, f3 = bl * g.kappa;
-#pragma unroll
-                for (int ti = 0; ti < TRK; ++ti) {
-                    const int mt = wr + 4 * ti;
-                    if (mt >= NTK) continue;
-                    const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
-                    f32x4 v = phi[ti][tj], cv = comp[ti][tj];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float delta = fmaf(f1, dacc[ti][tj][r], fmaf(f2, ybc[r], -f3 * oacc[ti][tj][r]));
-                        // Kahan step; cmask = 0 turns it into the plain update
-                        const float y = delta - cv[r];
-                        const float tt = v[r] + y;
-                        cv[r] = ((tt - v[r]) - y) * cmask;
-                        v[r] = tt;
-                    }
-                    phi[ti][tj] = v;
-                    comp[ti][tj] = cv;
-                    M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
-                    if constexpr (M::kPhiT) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r] * live[tj]);
-                    }
-                }
-            }
-            if (s == g.spp - 1 || t + 1 == g.end_step) {
-                // non-finite values propagate through every later step, so one
-                // check per pass (and at the end of the run) sees any of them
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj)
-#pragma unroll
-                    for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) bad |= !isfinite(phi[ti][tj][r]);
-            }
-            if (Snap != nullptr && s == g.spp - 1) {   // end of a pass: Phi to the snapshot of this pass
-#pragma unroll
-                for (int tj = 0; tj < TC; ++tj)
-#pragma unroll
-                    for (int ti = 0; ti < TRK; ++ti) {
-                        const int mt = wr + 4 * ti, nt = wc + 2 * tj;
-                        if (mt >= NTK || nt >= NTK) continue;
-                        const int i = nt * 16 + l16;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int a = mt * 16 + 4 * q + r;
-                            if (a < k && i < k) Snap[(size_t)pass * k * k + (size_t)i * k + a] = phi[ti][tj][r];
-                        }
-                    }
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- write back the master copy (and compensation)
-#pragma unroll
-    for (int ti = 0; ti < TRK; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < TC; ++tj) {
-            const int mt = wr + 4 * ti, nt = wc + 2 * tj;
-            if (mt >= NTK || nt >= NTK) continue;
-            const int i = nt * 16 + l16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = mt * 16 + 4 * q + r;
-                if (a < k && i < k) {
-                    Phi[(size_t)i * k + a] = phi[ti][tj][r];
-                    if (Comp) Comp[(size_t)i * k + a] = g.compensated ? comp[ti][tj][r] : 0.0f;
-                }
-            }
-        }
-    if (bad && g.nonfinite) *g.nonfinite = 1;
+    __shared__ __attribute__((aligned(16))) SgdSmem<M, KP, NSTAGE, 4> sm;
+    sgd_body<M, KP, NSTAGE, 4, false>(g, blockIdx.x, sm);
 }
-
-constexpr size_t kLdsLimit = 160 * 1024;
 
 template <class M, int KP, int NSTAGE>
 int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
@@ -671,13 +21,8 @@ int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
 // staging that fits in LDS (one view when the three views alias).
 template <class M, int KP>
 int dispatch_staging(const SgdArgs& a, int restarts, bool aliased, hipStream_t st) {
-    if constexpr (smem_bytes<M, KP, 3>() <= kLdsLimit) {
-        if (!aliased) return launch_sgd<M, KP, 3>(a, restarts, st);
-    }
-    if constexpr (smem_bytes<M, KP, 1>() <= kLdsLimit) {
-        if (aliased) return launch_sgd<M, KP, 1>(a, restarts, st);
-    }
-    return launch_sgd<M, KP, 0>(a, restarts, st);
+    constexpr int s1 = staging_for<M, KP>(true), s3 = staging_for<M, KP>(false);
+    return aliased ? launch_sgd<M, KP, s1>(a, restarts, st) : launch_sgd<M, KP, s3>(a, restarts, st);
 }
 
 int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB, const void* YC,
@@ -686,39 +31,13 @@ int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* Y
                int32_t* nonfinite, hipStream_t st) {
     OTM_REQUIRE(p != nullptr, OTM_EINVAL, "params is NULL");
     OTM_REQUIRE(YA && YB && YC && ybar && Phi, OTM_EINVAL, "null data pointer");
-    OTM_REQUIRE(p->k >= 1 && p->batch >= 1 && n >= 1 && p->passes >= 1, OTM_ESHAPE,
-                "k, batch, n and passes must be positive");
-    OTM_REQUIRE(p->k <= kMaxK, OTM_ECAPACITY, "k exceeds the compiled capacity (128)");
-    OTM_REQUIRE(p->batch <= kMaxBatch, OTM_ECAPACITY, "batch exceeds the compiled capacity (128)");
     OTM_REQUIRE(restarts >= 1, OTM_ESHAPE, "restarts must be >= 1");
-    OTM_REQUIRE(p->ldy >= p->k, OTM_ESHAPE, "ldy < k");
-    OTM_REQUIRE(p->y_dtype == OTM_F32 || p->y_dtype == OTM_BF16, OTM_EDTYPE, "y_dtype must be F32 or BF16");
-    OTM_REQUIRE(p->y_dtype != OTM_BF16 || p->ldy % 8 == 0, OTM_ESHAPE, "BF16 rows need ldy % 8 == 0");
-    OTM_REQUIRE(p->y_dtype != OTM_F32 || p->ldy % 4 == 0, OTM_ESHAPE, "F32 rows need ldy % 4 == 0");
-    OTM_REQUIRE(p->beta_tau > 0.0, OTM_EINVAL, "beta_tau must be positive");
-    OTM_REQUIRE(std::isfinite(p->beta0) && std::isfinite(p->alpha0) && std::isfinite(p->theta) && p->alpha0 >= 0.0,
-                OTM_EINVAL, "alpha0, beta0, theta must be finite, alpha0 >= 0");
     SgdArgs a{};
+    int status = fill_scalars(n, p->k, p->ldy, p->alpha0, p, start_step, end_step, a);
+    if (status != OTM_OK) return status;
     a.YA = YA; a.YB = YB; a.YC = YC; a.ybar = ybar; a.perms = perms; a.perm_stride = perm_stride;
-    a.Phi = Phi; a.Phi_comp = Phi_comp; a.snapshots = snapshots; a.nonfinite = nonfinite;
-    a.n = n; a.k = p->k; a.batch = p->batch; a.passes = p->passes; a.ldy = p->ldy;
-    a.compensated = p->compensated ? 1 : 0;
-    const int64_t spp = (n + p->batch - 1) / p->batch;
-    const int64_t total = spp * p->passes;
-    OTM_REQUIRE(total < (int64_t(1) << 31), OTM_ECAPACITY, "passes * ceil(n / batch) must be < 2^31");
-    const int64_t end = end_step < 0 ? total : end_step;
-    OTM_REQUIRE(start_step >= 0 && start_step <= end && end <= total, OTM_ESHAPE,
-                "need 0 <= start_step <= end_step <= passes * ceil(n / batch)");
-    a.spp = static_cast<int32_t>(spp);
-    a.start_step = static_cast<int32_t>(start_step);
-    a.end_step = static_cast<int32_t>(end);
-    const double al = p->alpha0;
-    a.a = static_cast<float>((al + 1.0) * (al + 2.0) / 2.0);
-    a.b = static_cast<float>(al * (al + 1.0) / 2.0);
-    a.c = static_cast<float>(al * al);
-    a.kappa = static_cast<float>(0.5 * (1.0 + p->theta));
-    a.beta0 = static_cast<float>(p->beta0);
-    a.inv_tau = static_cast<float>(1.0 / p->beta_tau);
+    a.Phi0 = Phi; a.Phi = Phi; a.Phi_comp = Phi_comp; a.snapshots = snapshots; a.nonfinite = nonfinite;
+    a.score = nullptr;
     if (a.start_step == a.end_step && !Phi_comp) return OTM_OK;
     const bool aliased = (YA == YB) && (YB == YC);
     const int k = p->k;

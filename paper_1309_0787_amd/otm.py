@@ -52,6 +52,12 @@ class _SgdParams(ctypes.Structure):
                 ("beta_tau", _dbl)]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("YA", _vp), ("YB", _vp), ("YC", _vp), ("ybar", _vp), ("perms", _vp), ("perm_stride", _i64),
+                ("Phi0", _vp), ("Phi", _vp), ("score", _vp), ("n", _i32), ("k", _i32), ("ldy", _i32),
+                ("pad_", _i32), ("alpha0", _dbl)]
+
+
 _SIGS = {
     "otm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "otm_last_error": (ctypes.c_char_p, []),
@@ -73,6 +79,22 @@ _SIGS = {
     "otm_sgd_step": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "otm_sgd_run": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i64,
                                    _i64, _vp, _vp, _vp, _vp, _vp]),
+    "otm_sgd_score_workspace": (_sz, [_i32]),
+    "otm_sgd_score": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz,
+                                     _vp]),
+    "otm_sgd_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_SgdParams),
+                                            ctypes.c_char_p, _vp, _vp, ctypes.POINTER(_vp)]),
+    "otm_plan_size": (_sz, [_vp]),
+    "otm_plan_image": (_vp, [_vp]),
+    "otm_plan_groups": (_i32, [_vp]),
+    "otm_plan_group_info": (ctypes.c_int, [_vp, _i32] + [ctypes.POINTER(_i32)] * 4),
+    "otm_plan_free": (ctypes.c_int, [_vp]),
+    "otm_sgd_batched_workspace": (_sz, [_vp]),
+    "otm_sgd_batched": (ctypes.c_int, [_vp, _vp, _vp, _sz, _vp]),
+    "otm_sgd_batched_graph": (ctypes.c_int, [_vp, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "otm_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "otm_graph_destroy": (ctypes.c_int, [_vp]),
+    "otm_sgd_autotune": (ctypes.c_int, [ctypes.POINTER(_i32), _i32, _i32, ctypes.c_char_p, _vp]),
     "otm_unwhiten_workspace": (_sz, [_i32, _i32]),
     "otm_unwhiten_topics": (ctypes.c_int, [_vp, _i32, _i32, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "otm_recover_pi_workspace": (_sz, [_i32]),
@@ -268,6 +290,109 @@ def sgd_run(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, perms: torch.
                              perm_stride, restarts, start_step, end_step, _ptr(Phi), _ptr(Phi_comp),
                              _ptr(snapshots), _ptr(nonfinite), _stream(stream)))
     return Phi
+
+
+def sgd_score(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, Phi: torch.Tensor, restarts: int = 1,
+              stream=None) -> torch.Tensor:
+    """score_r = sum_ij (phi_i^T phi_j)^3 - 2 sum_i T(phi_i, phi_i, phi_i) for each of
+    the `restarts` factor matrices in Phi (restarts x k x k FP32); FP64 result."""
+    score = torch.empty(restarts, dtype=torch.float64, device=Phi.device)
+    ws = _ws(lib().otm_sgd_score_workspace(restarts), Phi.device)
+    cp = p.c()
+    _check(lib().otm_sgd_score(ctypes.byref(cp), n, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), _ptr(Phi), restarts,
+                               _ptr(score), _ptr(ws), ws.numel(), _stream(stream)))
+    return score
+
+
+@dataclass
+class Problem:
+    """One decomposition of a batched run: FP32 whitened views (n x ldy; the
+    three may be the same tensor), global means (3 x k), initial factors
+    (restarts x k x k) and optional permutations (restarts x passes x n int32)."""
+    YA: torch.Tensor
+    YB: torch.Tensor
+    YC: torch.Tensor
+    ybar3: torch.Tensor
+    Phi0: torch.Tensor
+    k: int
+    alpha0: float
+    perms: torch.Tensor | None = None
+
+
+class BatchedRun:
+    """A planned batched STGD run: results Phi[i] (restarts x k x k), scores[i]
+    (restarts) per problem and best (the lowest-score restart per problem).
+    run() enqueues it; capture() turns it into a replayable graph."""
+
+    def __init__(self, problems: list[Problem], restarts: int, p: SgdParams, tune_cache: str | None = None):
+        dev = problems[0].Phi0.device
+        self.device = dev
+        self.problems = problems
+        self.restarts = restarts
+        self.Phi = [torch.empty_like(P.Phi0) for P in problems]
+        self.scores = [torch.empty(restarts, dtype=torch.float64, device=dev) for _ in problems]
+        self.best = torch.empty(len(problems), dtype=torch.int32, device=dev)
+        self.nonfinite = torch.zeros(1, dtype=torch.int32, device=dev)
+        arr = (_Problem * len(problems))()
+        for i, P in enumerate(problems):
+            n, ldy = P.YA.shape
+            for t in (P.YA, P.YB, P.YC):
+                if t.dtype != torch.float32 or t.shape != (n, ldy):
+                    raise OtmError(-3, "batched views must be FP32 tensors of one shape")
+            if P.Phi0.shape != (restarts, P.k, P.k):
+                raise OtmError(-2, "Phi0 must be restarts x k x k")
+            stride = 0 if P.perms is None else P.perms[0].numel()
+            arr[i] = _Problem(_ptr(P.YA), _ptr(P.YB), _ptr(P.YC), _ptr(P.ybar3), _ptr(P.perms), stride,
+                              _ptr(P.Phi0), _ptr(self.Phi[i]), _ptr(self.scores[i]), n, P.k, ldy, 0,
+                              float(P.alpha0))
+        cp = p.c()
+        plan = _vp()
+        _check(lib().otm_sgd_batched_plan(arr, len(problems), restarts, ctypes.byref(cp),
+                                          tune_cache.encode() if tune_cache else None, _ptr(self.best),
+                                          _ptr(self.nonfinite), ctypes.byref(plan)))
+        self._plan = plan
+        nbytes = lib().otm_plan_size(plan)
+        image = ctypes.string_at(lib().otm_plan_image(plan), nbytes)
+        self.groups = lib().otm_plan_groups(plan)
+        self.image = torch.frombuffer(bytearray(image), dtype=torch.uint8).to(dev)
+        self.ws = _ws(lib().otm_sgd_batched_workspace(plan), dev)
+        self._graph = None
+
+    def run(self, stream=None):
+        _check(lib().otm_sgd_batched(self._plan, _ptr(self.image), _ptr(self.ws), self.ws.numel(), _stream(stream)))
+
+    def capture(self, stream: torch.cuda.Stream):
+        """Captures the launch sequence into a graph on `stream` (not the null stream)."""
+        g = _vp()
+        _check(lib().otm_sgd_batched_graph(self._plan, _ptr(self.image), _ptr(self.ws), self.ws.numel(),
+                                           _stream(stream), ctypes.byref(g)))
+        self._graph = g
+
+    def replay(self, stream=None):
+        if self._graph is None:
+            raise OtmError(-1, "no graph captured")
+        _check(lib().otm_graph_launch(self._graph, _stream(stream)))
+
+    def close(self):
+        if self._graph is not None:
+            _check(lib().otm_graph_destroy(self._graph))
+            self._graph = None
+        if getattr(self, "_plan", None) is not None:
+            lib().otm_plan_free(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def sgd_autotune(ks, batch: int, cache_path: str, stream=None):
+    """Times the batched kernel's tile layouts for each padded k of ks and
+    records the fastest in cache_path."""
+    arr = (_i32 * len(ks))(*[int(k) for k in ks])
+    _check(lib().otm_sgd_autotune(arr, len(ks), batch, cache_path.encode(), _stream(stream)))
 
 
 # ------------------------------------------------------------------ a6

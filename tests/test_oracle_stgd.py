@@ -188,3 +188,44 @@ def test_batch_of_one_is_the_lemma():
         upd = upd - beta * b * ((p @ yA) * (p @ yB) * ybar[2] + (p @ yA) * (p @ ybar[1]) * yC
                                 + (p @ ybar[0]) * (p @ yB) * yC)
         np.testing.assert_allclose(new[:, i], upd, atol=1e-14)
+
+
+def test_restart_score_is_residual_minus_constant():
+    """score = (R - 1) ||T||^2 with R from the explicitly formed difference tensor."""
+    k = 5
+    g = np.random.default_rng(9)
+    T = g.standard_normal((k, k, k))
+    tt = float(np.sum(T * T))
+    for _ in range(3):
+        Phi = g.standard_normal((k, k))
+        Sphi = np.einsum("ai,bi,ci->abc", Phi, Phi, Phi)
+        ref = float(np.sum((Sphi - T) ** 2)) - tt
+        assert abs(oracle.restart_score(T, Phi) - ref) < 1e-12 * (abs(ref) + tt)
+
+
+def test_best_restart_ties_and_order():
+    assert oracle.best_restart([3.0, 1.0, 1.0, 2.0]) == 1
+    assert oracle.best_restart([0.5]) == 0
+
+
+def test_batched_picks_a_restart_that_recovers_the_planted_factors():
+    """Exact moments: the restart with the lowest score reaches R = 0, i.e. the
+    planted factors (closed form of the fixed point); several restarts stall."""
+    d, k = 16, 4
+    mu, ahat, W = _exact_instance(d, k, seed=61)
+    Y = exact_samples(W, mu, ahat)
+    ybar = np.stack([Y.mean(0)] * 3)
+    T = oracle.whitened_tensor(Y, Y, Y, ybar, 0.0)
+    perms = np.tile(np.arange(k, dtype=np.int32), (3000, 1))
+    P = dict(YA=Y, YB=Y, YC=Y, ybar=ybar, alpha0=0.0,
+             Phi0=[synth.initial_factors(k, 5, r) for r in range(8)], perms=[perms] * 8)
+    (phis, scores, best), = oracle.sgd_batched([P], batch=k, beta0=0.05, tau=1e9)
+    tt = float(np.sum(T * T))
+    assert scores[best] == min(scores)
+    assert max(oracle.residual(T, P_) for P_ in phis) > 0.1      # some restarts stall
+    assert oracle.residual(T, phis[best]) < 1e-12
+    assert abs(scores[best] + tt) < 1e-10 * tt          # R = 0  <=>  score = -||T||^2
+    U, lam, Phi_star = planted_whitened_factors(W, mu, ahat)
+    # every planted factor is matched by one recovered column (up to order)
+    cos = np.abs((phis[best] / np.linalg.norm(phis[best], axis=0)).T @ U)
+    assert np.all(np.abs(np.sort(cos.max(axis=0)) - 1.0) < 1e-9)
