@@ -85,6 +85,83 @@ def cpu_baseline(inst, w):
                       f"{w['passes']} STGD passes, memberships; {el:.1f} s"}
 
 
+# beta0 3e-4: at 1e-3 the three-view problems with k = 100 and alpha0 = 1 diverge
+BATCHED = dict(problems=256, ks=(16, 32, 64, 100, 128), n_lo=1e3, n_hi=1e5, restarts=8, passes=50, batch=100,
+               beta0=3e-4, beta_tau=2500.0)
+PEAK_FP32_MFMA = 157.3e12
+
+
+def bench_batched(steps: int, warmup: int) -> dict:
+    """Many decompositions with restarts in one launch (FP32): 256 problems, k
+    uniform over {16, 32, 64, 100, 128}, n log-uniform in [1e3, 1e5], half
+    three-view (documents) and half one-view (graphs), 8 restarts each; the
+    tile layouts come from the autotuner (run first, timed separately)."""
+    import tempfile
+
+    import numpy as np
+    import torch
+    from paper_1309_0787_amd import otm
+    import synth
+
+    w = BATCHED
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    table = synth.batched_table(w["problems"], w["ks"], w["n_lo"], w["n_hi"])
+    problems = []
+    for i, sp in enumerate(table):
+        k, n = sp["k"], sp["n"]
+        ldy = otm.default_ldy(k)
+        YA, YB, YC, _ = synth.planted_views(n, k, sp["alpha0"], sp["views"], sub=i, device=dev, ldy=ldy)
+        ybar = torch.stack([YA[:, :k].mean(0), YB[:, :k].mean(0), YC[:, :k].mean(0)]).contiguous()
+        Phi0 = torch.as_tensor(np.stack([synth.initial_factors(k, restart=r + 100 * i).T for r in range(w["restarts"])]),
+                               dtype=torch.float32, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(1000 + i)
+        perms = torch.argsort(torch.rand((w["passes"], n), device=dev, generator=g), dim=1).to(torch.int32)
+        problems.append(otm.Problem(YA, YB, YC, ybar, Phi0, k, sp["alpha0"], perms))   # perms shared by the restarts
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    p = otm.SgdParams(k=1, batch=w["batch"], passes=w["passes"], y_dtype=otm.F32, beta0=w["beta0"],
+                      beta_tau=w["beta_tau"])
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tune.txt")
+        t0 = time.perf_counter()
+        otm.sgd_autotune(sorted(set(w["ks"])), w["batch"], cache)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+        tuned = open(cache).read().splitlines()[1:]
+        run = otm.BatchedRun(problems, w["restarts"], p, tune_cache=cache)
+    for _ in range(warmup):
+        run.run()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        run.run()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    samples = sum(sp["n"] for sp in table) * w["passes"] * w["restarts"]
+    flops = 0.0
+    for sp in table:
+        full, rem = divmod(sp["n"], w["batch"])
+        per_pass = full * (6.0 * w["batch"] * sp["k"] ** 2 + 4.0 * sp["k"] ** 3)
+        if rem:
+            per_pass += 6.0 * rem * sp["k"] ** 2 + 4.0 * sp["k"] ** 3
+        flops += per_pass * (w["passes"] + 1) * w["restarts"]     # training passes + the scoring pass
+    achieved = flops / (ms * 1e-3)
+    return {
+        "workload": f"{w['problems']} problems, k in {list(w['ks'])}, n log-uniform [{int(w['n_lo'])}, {int(w['n_hi'])}], "
+                    f"half three-view / half one-view, {w['restarts']} restarts, {w['passes']} passes, FP32",
+        "samples_per_s": samples / (ms * 1e-3), "ms_per_run": ms, "jobs": len(problems) * w["restarts"],
+        "kernel_groups": run.groups,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_MFMA, "flops_per_run": flops},
+        "nonfinite": int(run.nonfinite.item()), "generation_s": round(t_gen, 2), "autotune_s": round(t_tune, 2),
+        "tuned_layouts": tuned,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +169,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quality", action="store_true", help="also report the residual of the final factors")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched many-problem measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path is single-GPU here",
@@ -175,7 +253,11 @@ def main():
         T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
         out["quality"] = {"residual": float(otm.residual(T, res.Phi[0]).item()),
                           "nonfinite": int(res.nonfinite.item())}
+    if not args.no_batched:
+        print("bench: batched workload", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1)
     if not args.no_cpu_baseline:
+        print("bench: oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, w)
     print(json.dumps(out), flush=True)
 

@@ -213,7 +213,8 @@ int otm_sgd_score(const otm_sgd_params* p, int32_t n, const void* YA, const void
  * A problem is one decomposition: whitened views of n rows, k components,
  * `restarts` runs from the initial factors Phi0 + r*k*k, results Phi + r*k*k,
  * scores score[r] as in otm_sgd_score of the final factors.  perms: NULL
- * (rows in order) or, per run r, passes x n int32 at perms + r*perm_stride.
+ * (rows in order) or, per run r, passes x n int32 at perms + r*perm_stride
+ * (perm_stride 0: every run of the problem visits the rows in the same order).
  * Every pointer is device memory owned by the caller. */
 typedef struct {
     const void* YA;

@@ -246,8 +246,9 @@ int fill_problem_job(const otm_problem& P, const otm_sgd_params* p, int restarts
     std::memset(&J, 0, sizeof J);
     int s = fill_scalars(P.n, P.k, P.ldy, P.alpha0, p, 0, -1, J.args);
     if (s != OTM_OK) return s;
-    OTM_REQUIRE(P.perms == nullptr || restarts == 1 || P.perm_stride >= (int64_t)p->passes * P.n, OTM_ESHAPE,
-                "perm_stride must be >= passes * n");
+    OTM_REQUIRE(P.perms == nullptr || restarts == 1 || P.perm_stride == 0 ||
+                    P.perm_stride >= (int64_t)p->passes * P.n,
+                OTM_ESHAPE, "perm_stride must be 0 (shared) or >= passes * n");
     SgdArgs& a = J.args;
     a.YA = P.YA; a.YB = P.YB; a.YC = P.YC; a.ybar = P.ybar; a.perms = P.perms; a.perm_stride = P.perm_stride;
     a.Phi0 = P.Phi0; a.Phi = P.Phi; a.Phi_comp = nullptr; a.snapshots = nullptr; a.score = P.score;

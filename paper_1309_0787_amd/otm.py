@@ -308,7 +308,8 @@ def sgd_score(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, Phi: torch.
 class Problem:
     """One decomposition of a batched run: FP32 whitened views (n x ldy; the
     three may be the same tensor), global means (3 x k), initial factors
-    (restarts x k x k) and optional permutations (restarts x passes x n int32)."""
+    (restarts x k x k) and optional permutations (int32, restarts x passes x n,
+    or passes x n shared by every restart)."""
     YA: torch.Tensor
     YB: torch.Tensor
     YC: torch.Tensor
@@ -341,7 +342,8 @@ class BatchedRun:
                     raise OtmError(-3, "batched views must be FP32 tensors of one shape")
             if P.Phi0.shape != (restarts, P.k, P.k):
                 raise OtmError(-2, "Phi0 must be restarts x k x k")
-            stride = 0 if P.perms is None else P.perms[0].numel()
+            # perms: restarts x passes x n (one order per run) or passes x n (shared)
+            stride = 0 if P.perms is None or P.perms.dim() == 2 else P.perms[0].numel()
             arr[i] = _Problem(_ptr(P.YA), _ptr(P.YB), _ptr(P.YC), _ptr(P.ybar3), _ptr(P.perms), stride,
                               _ptr(P.Phi0), _ptr(self.Phi[i]), _ptr(self.scores[i]), n, P.k, ldy, 0,
                               float(P.alpha0))

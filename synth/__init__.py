@@ -269,6 +269,56 @@ def dirichlet_alpha(k: int, alpha0: float) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Batched workload: many problems of whitened rows from a planted mixture
+# --------------------------------------------------------------------------
+def batched_table(n_problems: int = 256, ks=(16, 32, 64, 100, 128), n_lo: float = 1e3, n_hi: float = 1e5,
+                  seed: int = BASE_SEED) -> list[dict]:
+    """Shapes of the batched workload: k uniform over ks, n log-uniform in
+    [n_lo, n_hi], half document-like problems (three views, alpha0 = 1) and half
+    graph-like (one view, alpha0 = 0.1 up to n = 1e4, else 0.5), in random order."""
+    g = rng(seed, S_MISC, 1)
+    k = g.choice(np.asarray(ks), size=n_problems)
+    n = np.exp(g.uniform(np.log(n_lo), np.log(n_hi), size=n_problems)).astype(np.int64)
+    kinds = np.array(["lda"] * (n_problems // 2) + ["mmsb"] * (n_problems - n_problems // 2))
+    g.shuffle(kinds)
+    out = []
+    for i in range(n_problems):
+        a0 = 1.0 if kinds[i] == "lda" else (0.1 if n[i] <= 10_000 else 0.5)
+        out.append(dict(kind=str(kinds[i]), n=int(n[i]), k=int(k[i]), alpha0=a0, views=3 if kinds[i] == "lda" else 1))
+    return out
+
+
+def planted_views(n: int, k: int, alpha0: float, views: int, seed: int = BASE_SEED, sub: int = 0,
+                  device="cpu", noise: float = 0.3, ldy: int | None = None):
+    """Whitened rows of a planted mixture, generated with torch on `device`:
+    h_t ~ Dir(alpha0/k 1), M = sqrt(k) U with U a Haar orthonormal k x k matrix
+    (the whitened topic directions when every alpha_i is alpha0/k), and for each
+    view independently y_t = M h_t + (noise / sqrt(k)) N(0, I).  Returns the
+    views as float32 tensors n x ldy (zero columns beyond k; one tensor three
+    times when views == 1) and U.  Seeded: the torch generators are forked."""
+    import torch
+    ldy = ldy or k
+    dev = torch.device(device)
+    U = torch.as_tensor(initial_factors(k, seed, restart=10_000 + sub), dtype=torch.float32)
+    M = (np.sqrt(k) * U).to(dev)
+    devices = [dev] if dev.type == "cuda" else []
+    with torch.random.fork_rng(devices=devices):
+        torch.manual_seed(int(rng(seed, S_MISC, 2 + sub).integers(1 << 62)))
+        conc = torch.full((k,), alpha0 / k, device=dev)
+        h = torch.distributions.Dirichlet(conc).sample((n,))
+        h = torch.nan_to_num(h, nan=1.0 / k)           # all-zero gamma draws at tiny alpha
+        mean = h @ M.T
+        out = []
+        for _ in range(views):
+            y = torch.zeros((n, ldy), dtype=torch.float32, device=dev)
+            y[:, :k] = mean + (noise / np.sqrt(k)) * torch.randn((n, k), device=dev)
+            out.append(y)
+    if views == 1:
+        out = out * 3
+    return out[0], out[1], out[2], U
+
+
+# --------------------------------------------------------------------------
 # Configurations of the paper-shaped workloads
 # --------------------------------------------------------------------------
 CONFIGS = {
