@@ -287,6 +287,78 @@ int otm_graph_destroy(otm_graph graph);
  * probe buffers (setup time, not for capture); synchronises the stream. */
 int otm_sgd_autotune(const int32_t* ks, int32_t n_k, int32_t batch, const char* cache_path, otm_stream stream);
 
+/* ---- learned warm start of the stochastic updates (an addition: the paper
+ * starts them at random, Section 3.2) ----------------------------------------
+ * Sizes: P = 100 (largest k the network takes), 4 sketches, n_in = 4 P^2 +
+ * 4 P, hidden 512, n_out = P^2; the parameters are one flat FP32 buffer
+ * [W1 (hidden x n_in), b1 (hidden), W2 (n_out x hidden), b2 (n_out)],
+ * row-major. */
+int otm_ws_dims(int32_t* n_in, int32_t* n_hidden, int32_t* n_out, int32_t* p, int64_t* n_params);
+
+/* Sketch of the whitened third moment: S_r = T(I, I, theta_r), r = 0..3, the
+ * tensor T of Lemma "update" (global means ybar, coefficients of alpha0)
+ * contracted along its third (view C) mode, from the rows without forming T:
+ *   S_r = (1/n) YA^T diag(a z_r - b (ybarC . theta_r)) YB - b ybarA (YB^T z_r / n)^T
+ *         - b (YA^T z_r / n) ybarB^T + c (ybarC . theta_r) ybarA ybarB^T,  z_r = YC theta_r.
+ * Rows n x ldy in y_dtype (F32 or BF16); ybar 3 x k FP32; Theta k x 4 FP32
+ * row-major; S: 4 blocks of lds x lds FP32 (S_r[i][j] at S + (r*lds + i)*lds
+ * + j; entries outside the k x k block untouched).  FP64 sums, FP32 output. */
+size_t otm_ws_sketch_workspace(int32_t n, int32_t k);
+int otm_ws_sketch(const void* YA, const void* YB, const void* YC, int y_dtype, int32_t ldy, int32_t n, int32_t k,
+                  const float* ybar, double alpha0, const float* Theta, float* S, int32_t lds, void* ws,
+                  size_t ws_bytes, otm_stream stream);
+
+/* Canonical frames and network inputs for `count` instances (one workgroup
+ * each): ks[i] (device int32, 1 <= k <= P); S: count x 4 x P x P sketches
+ * (live k x k blocks); Theta: count x P x 4.  Q (count x P x P): the
+ * eigenvectors of sym(S_0) as columns (FP32 Jacobi), by decreasing
+ * |eigenvalue| (ties: lower index), each oriented so that its contraction with
+ * the theta_r of largest |q . theta_r| has the sign of q^T S_r q; zero
+ * outside k x k.  sigma: sqrt(mean_r ||S_r||_F^2).  X (count x n_in):
+ * [Q^T S_r Q / sigma padded to P x P for r = 0..3, Q^T theta_r padded to P].
+ * info[i]: Jacobi sweeps used, -1 if not converged in 15, -2 if k is out of
+ * range (then X = 0, Q = I).  ws: otm_ws_frames_workspace(count). */
+size_t otm_ws_frames_workspace(int32_t count);
+int otm_ws_frames(int32_t count, const int32_t* ks, const float* S, const float* Theta, float* Q, float* sigma,
+                  float* X, int32_t* info, void* ws, size_t ws_bytes, otm_stream stream);
+
+/* Training targets: with the planted directions U (count x P x P, column j =
+ * u_j) and lambda (count x P), C = Q^T U, perm = greedy matching by
+ * decreasing |C| (ties: lower row, then lower column), target (count x P^2,
+ * row-major P x P) column l = lambda_perm[l]^(1/3) C[:, perm[l]] / sigma^(1/3). */
+int otm_ws_target(int32_t count, const int32_t* ks, const float* Q, const float* sigma, const float* U,
+                  const float* lam, float* target, otm_stream stream);
+
+/* Perceptron on the matrix cores.  Forward (FP32): H = relu(X W1^T + b1)
+ * (batch x hidden), out = H W2^T + b2 (batch x n_out).  Backward from dout:
+ * grads (flat, as the parameters) of W2, b2, W1, b1.  Adam (Kingma and Ba,
+ * Algorithm 1) over the flat buffers, step t >= 1.  BF16 inference: weights
+ * converted once (otm_mlp_to_bf16), inputs and the hidden layer rounded to
+ * BF16, FP32 accumulation and FP32 biases (the FP32 parameter buffer). */
+size_t otm_mlp_workspace(int32_t batch);
+int otm_mlp_forward(const float* params, int32_t batch, const float* X, float* H, float* out, void* ws,
+                    size_t ws_bytes, otm_stream stream);
+int otm_mlp_backward(const float* params, int32_t batch, const float* X, const float* H, const float* dout,
+                     float* grads, void* ws, size_t ws_bytes, otm_stream stream);
+int otm_mlp_adam(float* params, const float* grads, float* m, float* v, int32_t t, double lr, double beta1,
+                 double beta2, double eps, otm_stream stream);
+int otm_mlp_to_bf16(const float* params, void* params_bf16, otm_stream stream);
+size_t otm_mlp_bf16_workspace(int32_t batch);
+int otm_mlp_forward_bf16(const void* params_bf16, const float* params, int32_t batch, const float* X, float* out,
+                         void* ws, size_t ws_bytes, otm_stream stream);
+
+/* Squared error over the live k x k blocks: *loss (device FP64) = sum / live,
+ * dout = 2 (out - target) / live inside the blocks, 0 outside; live = sum of
+ * k_i^2.  ws: otm_ws_mse_workspace(count). */
+size_t otm_ws_mse_workspace(int32_t count);
+int otm_ws_mse(int32_t count, const int32_t* ks, int64_t live, const float* out, const float* target, double* loss,
+               float* dout, void* ws, size_t ws_bytes, otm_stream stream);
+
+/* Initial factors V0 = Q out[:k, :k] sigma^(1/3): instance i writes phi_j
+ * (length k, contiguous) at Phi + i*P*P + j*k. */
+int otm_ws_factors(int32_t count, const int32_t* ks, const float* out, const float* Q, const float* sigma,
+                   float* Phi, otm_stream stream);
+
 /* ---- a6: post-processing (Section 3.3, Lemma "postprocessing") -----------
  * lambda_i = kappa ||phi_i||^3, u_i = phi_i / ||phi_i||,
  * mu_i = lambda_i (W^T)^+ u_i with (W^T)^+ = W (W^T W)^(-1), negatives

@@ -95,6 +95,23 @@ _SIGS = {
     "otm_graph_launch": (ctypes.c_int, [_vp, _vp]),
     "otm_graph_destroy": (ctypes.c_int, [_vp]),
     "otm_sgd_autotune": (ctypes.c_int, [ctypes.POINTER(_i32), _i32, _i32, ctypes.c_char_p, _vp]),
+    "otm_ws_dims": (ctypes.c_int, [ctypes.POINTER(_i32)] * 4 + [ctypes.POINTER(_i64)]),
+    "otm_ws_sketch_workspace": (_sz, [_i32, _i32]),
+    "otm_ws_sketch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _vp, _vp, _i32, _vp,
+                                     _sz, _vp]),
+    "otm_ws_frames_workspace": (_sz, [_i32]),
+    "otm_ws_frames": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_ws_target": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "otm_mlp_workspace": (_sz, [_i32]),
+    "otm_mlp_forward": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_mlp_backward": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _dbl, _dbl, _dbl, _dbl, _vp]),
+    "otm_mlp_to_bf16": (ctypes.c_int, [_vp, _vp, _vp]),
+    "otm_mlp_bf16_workspace": (_sz, [_i32]),
+    "otm_mlp_forward_bf16": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "otm_ws_mse_workspace": (_sz, [_i32]),
+    "otm_ws_mse": (ctypes.c_int, [_i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_ws_factors": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "otm_unwhiten_workspace": (_sz, [_i32, _i32]),
     "otm_unwhiten_topics": (ctypes.c_int, [_vp, _i32, _i32, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "otm_recover_pi_workspace": (_sz, [_i32]),
@@ -134,6 +151,9 @@ def _ptr(t) -> int | None:
         return None
     if not t.is_cuda:
         raise OtmError(-1, "tensor must live on the GPU")
+    if not t.is_contiguous():
+        # the library reads dense row-major buffers; a strided view would be misread
+        raise OtmError(-1, "tensor must be contiguous (row-major)")
     return t.data_ptr()
 
 
@@ -438,3 +458,106 @@ def residual(T: torch.Tensor, Phis: torch.Tensor, stream=None):
     ws = _ws(lib().otm_residual_workspace(k, cnt), T.device)
     _check(lib().otm_residual(_ptr(T), k, _ptr(Phis), cnt, _ptr(R), _ptr(ws), ws.numel(), _stream(stream)))
     return R
+
+
+# ------------------------------------------------------------------ warm start
+def ws_dims() -> dict:
+    v = [_i32() for _ in range(4)]
+    npar = _i64()
+    _check(lib().otm_ws_dims(*[ctypes.byref(x) for x in v], ctypes.byref(npar)))
+    return {"n_in": v[0].value, "hidden": v[1].value, "n_out": v[2].value, "P": v[3].value, "n_params": npar.value}
+
+
+def ws_sketch(YA, YB, YC, k: int, ybar3: torch.Tensor, alpha0: float, Theta: torch.Tensor, S: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """S_r = T(I, I, theta_r), r = 0..3 (4 x lds x lds FP32; lds = S.shape[-1])."""
+    n, ldy = YA.shape
+    if S is None:
+        S = torch.zeros((4, k, k), dtype=torch.float32, device=YA.device)
+    lds = S.shape[-1]
+    ws = _ws(lib().otm_ws_sketch_workspace(n, k), YA.device)
+    _check(lib().otm_ws_sketch(_ptr(YA), _ptr(YB), _ptr(YC), _DTYPE_CODE[YA.dtype], ldy, n, k, _ptr(ybar3),
+                               float(alpha0), _ptr(Theta), _ptr(S), lds, _ptr(ws), ws.numel(), _stream(stream)))
+    return S
+
+
+def ws_frames(ks: torch.Tensor, S: torch.Tensor, Theta: torch.Tensor, stream=None):
+    """Canonical frames and network inputs: returns (Q, sigma, X, info)."""
+    d = ws_dims()
+    cnt = ks.numel()
+    dev = S.device
+    Q = torch.empty((cnt, d["P"], d["P"]), dtype=torch.float32, device=dev)
+    sig = torch.empty(cnt, dtype=torch.float32, device=dev)
+    X = torch.empty((cnt, d["n_in"]), dtype=torch.float32, device=dev)
+    info = torch.empty(cnt, dtype=torch.int32, device=dev)
+    ws = _ws(lib().otm_ws_frames_workspace(cnt), dev)
+    _check(lib().otm_ws_frames(cnt, _ptr(ks), _ptr(S), _ptr(Theta), _ptr(Q), _ptr(sig), _ptr(X), _ptr(info), _ptr(ws),
+                               ws.numel(), _stream(stream)))
+    return Q, sig, X, info
+
+
+def ws_target(ks, Q, sigma, U, lam, stream=None) -> torch.Tensor:
+    cnt = ks.numel()
+    P = Q.shape[-1]
+    tgt = torch.empty((cnt, P * P), dtype=torch.float32, device=Q.device)
+    _check(lib().otm_ws_target(cnt, _ptr(ks), _ptr(Q), _ptr(sigma), _ptr(U), _ptr(lam), _ptr(tgt), _stream(stream)))
+    return tgt
+
+
+def mlp_forward(params, X, stream=None):
+    d = ws_dims()
+    B = X.shape[0]
+    H = torch.empty((B, d["hidden"]), dtype=torch.float32, device=X.device)
+    out = torch.empty((B, d["n_out"]), dtype=torch.float32, device=X.device)
+    ws = _ws(lib().otm_mlp_workspace(B), X.device)
+    _check(lib().otm_mlp_forward(_ptr(params), B, _ptr(X), _ptr(H), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return H, out
+
+
+def mlp_backward(params, X, H, dout, grads=None, stream=None):
+    B = X.shape[0]
+    if grads is None:
+        grads = torch.empty_like(params)
+    ws = _ws(lib().otm_mlp_workspace(B), X.device)
+    _check(lib().otm_mlp_backward(_ptr(params), B, _ptr(X), _ptr(H), _ptr(dout), _ptr(grads), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return grads
+
+
+def mlp_adam(params, grads, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().otm_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream(stream)))
+
+
+def mlp_to_bf16(params, stream=None) -> torch.Tensor:
+    pb = torch.empty(params.numel(), dtype=torch.bfloat16, device=params.device)
+    _check(lib().otm_mlp_to_bf16(_ptr(params), _ptr(pb), _stream(stream)))
+    return pb
+
+
+def mlp_forward_bf16(params_bf16, params, X, stream=None) -> torch.Tensor:
+    d = ws_dims()
+    B = X.shape[0]
+    out = torch.empty((B, d["n_out"]), dtype=torch.float32, device=X.device)
+    ws = _ws(lib().otm_mlp_bf16_workspace(B), X.device)
+    _check(lib().otm_mlp_forward_bf16(_ptr(params_bf16), _ptr(params), B, _ptr(X), _ptr(out), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+    return out
+
+
+def ws_mse(ks, live: int, out, target, stream=None):
+    cnt = ks.numel()
+    loss = torch.empty(1, dtype=torch.float64, device=out.device)
+    dout = torch.empty_like(out)
+    ws = _ws(lib().otm_ws_mse_workspace(cnt), out.device)
+    _check(lib().otm_ws_mse(cnt, _ptr(ks), int(live), _ptr(out), _ptr(target), _ptr(loss), _ptr(dout), _ptr(ws),
+                            ws.numel(), _stream(stream)))
+    return loss, dout
+
+
+def ws_factors(ks, out, Q, sigma, stream=None) -> torch.Tensor:
+    cnt = ks.numel()
+    P = Q.shape[-1]
+    Phi = torch.zeros((cnt, P * P), dtype=torch.float32, device=out.device)
+    _check(lib().otm_ws_factors(cnt, _ptr(ks), _ptr(out), _ptr(Q), _ptr(sigma), _ptr(Phi), _stream(stream)))
+    return Phi
