@@ -113,7 +113,7 @@ def bench_batched(steps: int, warmup: int) -> dict:
         ldy = otm.default_ldy(k)
         YA, YB, YC, _ = synth.planted_views(n, k, sp["alpha0"], sp["views"], sub=i, device=dev, ldy=ldy)
         ybar = torch.stack([YA[:, :k].mean(0), YB[:, :k].mean(0), YC[:, :k].mean(0)]).contiguous()
-        Phi0 = torch.as_tensor(np.stack([synth.initial_factors(k, restart=r + 100 * i).T for r in range(w["restarts"])]),
+        Phi0 = torch.as_tensor(np.ascontiguousarray(np.stack([synth.initial_factors(k, restart=r + 100 * i).T for r in range(w["restarts"])])),
                                dtype=torch.float32, device=dev)
         g = torch.Generator(device=dev)
         g.manual_seed(1000 + i)
@@ -162,6 +162,93 @@ def bench_batched(steps: int, warmup: int) -> dict:
     }
 
 
+WARM = dict(instances=8000, epochs=15, batch=256, lr=1e-3, exact_share=0.8, sampled_n=2000)
+
+
+def recovery_error(Pi: "torch.Tensor", pi_true: "np.ndarray") -> float:
+    """||Pi_hat - pi^T||_F / ||pi||_F after matching communities (Hungarian on correlations)."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    P = Pi.detach().double().cpu().numpy()                     # k x n
+    T = pi_true.T                                              # k x n
+    Pc = P - P.mean(1, keepdims=True)
+    Tc = T - T.mean(1, keepdims=True)
+    corr = (Pc @ Tc.T) / (np.linalg.norm(Pc, axis=1)[:, None] * np.linalg.norm(Tc, axis=1)[None, :] + 1e-300)
+    r, c = linear_sum_assignment(-corr)
+    M = np.zeros_like(T)
+    M[c] = P[r]
+    return float(np.linalg.norm(M - T) / np.linalg.norm(T))
+
+
+def bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w) -> dict:
+    """Time to the converged loss: FP32 path from random factors against the
+    BF16 path from the learned warm start, on the benchmark graph.  R(Phi) is
+    evaluated at every pass end from snapshots, outside the timed stages; the
+    threshold is the FP32 path's final R plus 1e-3.  The warm start is trained
+    first (timed separately) on exact-moment instances (k in {10, 50, 100}) and
+    planted-mixture rows."""
+    import numpy as np
+    import torch
+    from paper_1309_0787_amd import otm, pipeline
+    from paper_1309_0787_amd import warmstart as pws
+
+    dev = torch.device("cuda:0")
+    ws_cfg = WARM
+    g = np.random.default_rng(0)
+    specs = []
+    for i in range(ws_cfg["instances"]):
+        if g.random() < ws_cfg["exact_share"]:
+            specs.append(dict(k=int(g.choice([10, 50, 100, 100, 100])), seed=5000 + i, kind="exact"))
+        else:
+            specs.append(dict(k=w["k"], seed=5000 + i, kind="sampled", n=ws_cfg["sampled_n"], alpha0=w["alpha0"],
+                              views=1))
+    t0 = time.perf_counter()
+    tr = pws.build_instances(specs, dev)
+    warm = pws.WarmStart(dev, seed=3)
+    _, _, X, tgt, _ = warm.prepare(tr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = warm.train(X, tgt, tr.ks, epochs=ws_cfg["epochs"], batch=ws_cfg["batch"], lr=ws_cfg["lr"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del X, tgt, tr
+    k = w["k"]
+    runs = {}
+    pi_true = inst.pi[inst.X]
+    for name, ydt, use_warm in (("fp32_random", otm.F32, False), ("bf16_warm", otm.BF16, True)):
+        cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=ydt,
+                                 batch=w["batch"], passes=w["passes"], beta0=w["beta0"], beta_tau=w["beta_tau"],
+                                 tau_pi=w["tau_pi"])
+        Phi = Phi_init.clone()
+        tm = pipeline.Timer(True)
+        res = pipeline.fit([C], C, CT, S, Phi, perms, cfg, pi_view=0, snapshots=True, timer=tm,
+                           warm=warm if use_warm else None)
+        torch.cuda.synchronize()
+        spans = tm.spans_ms()
+        T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
+        Rs = otm.residual(T, res.snapshots[0].contiguous()).cpu().numpy()
+        runs[name] = dict(stages_ms={a: round(b, 3) for a, b in spans.items()}, R_by_pass=[float(x) for x in Rs],
+                          recovery_error=recovery_error(res.Pi, pi_true))
+    r_inf = runs["fp32_random"]["R_by_pass"][-1]
+    thr = r_inf + 1e-3
+    out = {"threshold": thr, "R_inf_fp32": r_inf}
+    for name, r in runs.items():
+        hit = [i for i, x in enumerate(r["R_by_pass"]) if x <= thr]
+        passes = hit[0] + 1 if hit else None
+        st = r["stages_ms"]
+        prefix = st.get("sketch", 0) + st.get("whitener", 0) + st.get("whiten", 0) + st.get("warm", 0)
+        ttl = prefix + st["stgd"] * passes / w["passes"] if passes else None
+        out[name] = {"time_to_loss_ms": ttl, "passes_to_loss": passes, "R_final": r["R_by_pass"][-1],
+                     "R_pass1": r["R_by_pass"][0], "stgd_ms_50_passes": st["stgd"], "prefix_ms": prefix,
+                     "warm_ms": st.get("warm"), "recovery_error": r["recovery_error"]}
+    a, b = out["fp32_random"]["time_to_loss_ms"], out["bf16_warm"]["time_to_loss_ms"]
+    out["speedup"] = (a / b) if (a and b) else None
+    out["warm_start"] = {"train_instances": ws_cfg["instances"], "epochs": ws_cfg["epochs"],
+                         "build_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                         "final_loss": float(np.mean(losses[-10:])), "adam_steps": len(losses)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +257,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quality", action="store_true", help="also report the residual of the final factors")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-problem measurement")
+    ap.add_argument("--no-time-to-loss", action="store_true", help="skip the warm-start time-to-loss measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path is single-GPU here",
@@ -253,6 +341,9 @@ def main():
         T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
         out["quality"] = {"residual": float(otm.residual(T, res.Phi[0]).item()),
                           "nonfinite": int(res.nonfinite.item())}
+    if not args.no_time_to_loss:
+        print("bench: time to loss, BF16 + warm start against FP32", file=sys.stderr, flush=True)
+        out["time_to_loss"] = bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w)
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1)

@@ -350,7 +350,7 @@ class BatchedRun:
         self.device = dev
         self.problems = problems
         self.restarts = restarts
-        self.Phi = [torch.empty_like(P.Phi0) for P in problems]
+        self.Phi = [torch.empty(P.Phi0.shape, dtype=torch.float32, device=dev) for P in problems]
         self.scores = [torch.empty(restarts, dtype=torch.float64, device=dev) for _ in problems]
         self.best = torch.empty(len(problems), dtype=torch.int32, device=dev)
         self.nonfinite = torch.zeros(1, dtype=torch.int32, device=dev)

@@ -67,12 +67,15 @@ class Timer:
 
 
 def fit(views, C_m2, CT_m2, S: torch.Tensor, Phi0: torch.Tensor, perms: torch.Tensor | None, cfg: FitConfig,
-        pi_view=None, snapshots: bool = False, timer: Timer | None = None) -> FitResult:
+        pi_view=None, snapshots: bool = False, timer: Timer | None = None, warm=None,
+        warm_seed: int = 0) -> FitResult:
     """views: 1 DeviceCSR (graph: the three views alias) or 3 (document views A, B, C).
     C_m2/CT_m2: the observations the second moment is built from and their transpose.
     Phi0: restarts x k x k FP32 (row i = phi_i), consumed in place.
     perms: passes x n int32 shared by the restarts, or restarts x passes x n.
-    pi_view: index of the view whose rows get memberships (graphs), or None."""
+    pi_view: index of the view whose rows get memberships (graphs), or None.
+    warm: a trained warmstart.WarmStart; its factors replace Phi0[0] (the
+    other restarts keep theirs)."""
     t = timer or Timer(False)
     k = cfg.k
     t.mark("start")
@@ -90,6 +93,9 @@ def fit(views, C_m2, CT_m2, S: torch.Tensor, Phi0: torch.Tensor, perms: torch.Te
         ybars = ybars * 3
     ybar3 = torch.cat(ybars).contiguous()
     t.mark("whiten")
+    if warm is not None:
+        Phi0[0].copy_(warm.initial_factors(ys[0], ys[1], ys[2], ybar3, k, cfg.alpha0, seed=warm_seed))
+        t.mark("warm")
     n = views[0].n_rows
     p = otm.SgdParams(k=k, batch=cfg.batch, passes=cfg.passes, y_dtype=cfg.y_dtype, compensated=cfg.compensated,
                       alpha0=cfg.alpha0, theta=cfg.theta, beta0=cfg.beta0, beta_tau=cfg.beta_tau,
