@@ -44,8 +44,11 @@ def sgd_flops(n: int, batch: int, k: int, passes: int) -> float:
 
 
 def kernel_hash() -> str:
-    src = open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", "stgd.hip"), "rb").read()
-    return hashlib.sha256(src).hexdigest()[:16]
+    """Hash of the STGD kernel's sources (the counters are valid for these only)."""
+    h = hashlib.sha256()
+    for f in ("stgd.hip", "stgd_kernel.h"):
+        h.update(open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def counters_traffic():
@@ -258,7 +261,22 @@ def main():
     ap.add_argument("--quality", action="store_true", help="also report the residual of the final factors")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-problem measurement")
     ap.add_argument("--no-time-to-loss", action="store_true", help="skip the warm-start time-to-loss measurement")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES three times (scale for the HBM counters)")
+    ap.add_argument("--print-kernel-hash", action="store_true", help="print the STGD kernel source hash and exit")
     args = ap.parse_args()
+    if args.print_kernel_hash:
+        print(kernel_hash())
+        return
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the hot path is single-GPU here",
               file=sys.stderr)

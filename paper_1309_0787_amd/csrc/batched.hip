@@ -4,14 +4,14 @@
 // tile layout chosen by the autotuner, view staging), longest job first in
 // every group.  A run enqueues, on one stream or into one graph:
 //   reset (queue counters, non-finite flag)
-//   -> one persistent kernel per group, all concurrent (forked branches):
-//      its workgroups pull jobs from the group's counter until it is empty
+//   -> one persistent kernel per group on up to four forked branches (as
+//      many as run side by side), groups balanced over the branches by
+//      estimated work; a kernel's workgroups pull jobs from its group's
+//      counter until it is empty
 //   -> selection of the best restart of every problem.
 // Each persistent kernel is its own instantiation, so its registers are
 // allocated for its variant alone and small-k variants keep more workgroups
-// per CU; the workgroups of a group are sized from the group's share of the
-// total estimated work so that the groups finish together.  Every job ends
-// with a scoring pass (the residual up to a constant).
+// per CU.  Every job ends with a scoring pass (the residual up to a constant).
 //
 // Variants (FP32 operands): padded k KP = 16, 32, ..., 128; wave grid 4 x 2
 // (layout 0) or, layout 1, 8 x 1 for KP <= 32 and 2 x 4 above; batch staging
@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kClasses = kMaxK / 16;          // KP = 16 (c + 1)
 constexpr int kVariants = kClasses * 2 * 2;   // x layout x view staging
-constexpr int kMaxBranches = 8;               // concurrent streams of one run
+constexpr int kMaxBranches = 4;               // concurrent streams of one run (hardware queues)
 
 __host__ __device__ constexpr int variant_id(int cls, int layout, int three_views) {
     return (cls * 2 + layout) * 2 + three_views;
@@ -263,16 +263,25 @@ int enqueue_plan(const otm_plan_s& P, const void* image, int32_t* counters, hipS
     const int ng = static_cast<int>(P.groups.size());
     hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, st, counters, ng, P.nonfinite);
     if ((s = check_launch("batched_reset_kernel")) != OTM_OK) return s;
-    // workgroups per group: the group's share of the device, by estimated work
-    double total = 0.0;
-    for (const auto& g : P.groups) total += g.work;
-    std::vector<int> grid(ng);
-    for (int i = 0; i < ng; ++i) {
+    // Branches: as many as a process's kernels run side by side (its hardware
+    // queues).  Groups go to the least loaded branch, largest estimated work
+    // first, and run one after another there; each kernel takes its branch's
+    // share of the device (its variant's resident workgroups over the number
+    // of branches, at most its job count).
+    const int nb = std::min(ng, kMaxBranches);
+    std::vector<int> order(ng), branch_of(ng), grid(ng);
+    for (int i = 0; i < ng; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return P.groups[x].work > P.groups[y].work; });
+    std::vector<double> load(nb, 0.0);
+    for (int i : order) {
+        const int b = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+        branch_of[i] = b;
+        load[b] += P.groups[i].work;
         int pc = 1;
         if ((s = per_cu(P.groups[i].variant, &pc)) != OTM_OK) return s;
-        const double share = total > 0.0 ? P.groups[i].work / total : 1.0 / ng;
-        const int want = static_cast<int>(std::ceil(share * cus * pc));
-        grid[i] = std::max(1, std::min(P.groups[i].count, std::max(want, 1)));
+        const int want = (cus * pc + nb - 1) / nb;
+        grid[i] = std::max(1, std::min(P.groups[i].count, want));
     }
     const BatchJob* jobs = static_cast<const BatchJob*>(image);
     const BatchProblem* probs =
@@ -287,12 +296,11 @@ int enqueue_plan(const otm_plan_s& P, const void* image, int32_t* counters, hipS
         if ((s = branches(&B)) != OTM_OK) return s;
         hipError_t e = hipEventRecord(B->fork, st);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        const int nb = std::min(ng, kMaxBranches);
         for (int b = 0; b < nb; ++b)
             if ((e = hipStreamWaitEvent(B->stream[b], B->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-        for (int i = 0; i < ng; ++i) {
+        for (int i : order) {
             const auto& g = P.groups[i];
-            hipLaunchKernelGGL(variant_kernel(g.variant), dim3(grid[i]), dim3(kThreads), 0, B->stream[i % nb],
+            hipLaunchKernelGGL(variant_kernel(g.variant), dim3(grid[i]), dim3(kThreads), 0, B->stream[branch_of[i]],
                                jobs + g.first, g.count, counters + i);
             if ((s = check_launch("sgd_persistent_kernel")) != OTM_OK) return s;
         }
