@@ -168,6 +168,52 @@ def bench_batched(steps: int, warmup: int) -> dict:
 WARM = dict(instances=8000, epochs=15, batch=256, lr=1e-3, exact_share=0.8, sampled_n=2000)
 
 
+def bench_spmm(reps: int = 20) -> dict:
+    """Whitening SpMM on the document workload (d = 10000, k = 50, 1e5
+    documents of Poisson(200) tokens, three views, FP32 counts, FP32 W and Y):
+    the HBM-bound case.  W is a seeded Gaussian d x k matrix (the values do not
+    change the work) in the whitener's layout (rows padded to 16 bytes).
+    Algorithmic bytes per view: nnz (4 + 4) + 4 (n + 1) + n ldy 4 written, plus
+    W (d k 4) once; the W rows gathered per entry come from L2."""
+    import numpy as np
+    import torch
+    from paper_1309_0787_amd import otm
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    inst = synth.make("lda_medium")
+    t_gen = time.perf_counter() - t0
+    k, d, n = 50, inst.C.n_cols, inst.C.n_rows
+    views = [otm.DeviceCSR.from_host(v, dev) for v in inst.views]
+    ldw = otm.default_ldw(k, otm.F32)
+    Wbuf = torch.zeros((d, ldw), dtype=torch.float32, device=dev)
+    Wbuf[:, :k] = torch.as_tensor(np.random.default_rng(0).standard_normal((d, k)), dtype=torch.float32, device=dev)
+    W = Wbuf[:, :k]
+    ldy = otm.default_ldy(k)
+    Ys = [torch.empty((n, ldy), dtype=torch.float32, device=dev) for _ in views]
+    for v, Y in zip(views, Ys):
+        otm.whiten(v, True, W, y_dtype=otm.F32, out=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for v, Y in zip(views, Ys):
+            otm.whiten(v, True, W, y_dtype=otm.F32, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps                       # three views
+    nnz = sum(v.nnz for v in inst.views)
+    algo = nnz * 8 + 3 * 4 * (n + 1) + 3 * n * ldy * 4 + d * k * 4
+    achieved = algo / (ms * 1e-3)
+    return {"workload": f"documents d={d}, k={k}, n={n}, three views, nnz={nnz}, FP32",
+            "ms_per_three_views": ms, "algorithmic_bytes": algo,
+            "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": achieved / PEAK_HBM},
+            "w_gather_bytes": nnz * ldw * 4, "w_gather_tb_per_s": nnz * ldw * 4 / (ms * 1e-3) / 1e12,
+            "generation_s": round(t_gen, 2)}
+
+
 def recovery_error(Pi: "torch.Tensor", pi_true: "np.ndarray") -> float:
     """||Pi_hat - pi^T||_F / ||pi||_F after matching communities (Hungarian on correlations)."""
     import numpy as np
@@ -261,6 +307,7 @@ def main():
     ap.add_argument("--quality", action="store_true", help="also report the residual of the final factors")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-problem measurement")
     ap.add_argument("--no-time-to-loss", action="store_true", help="skip the warm-start time-to-loss measurement")
+    ap.add_argument("--no-spmm", action="store_true", help="skip the document whitening SpMM measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (scale for the HBM counters)")
     ap.add_argument("--print-kernel-hash", action="store_true", help="print the STGD kernel source hash and exit")
@@ -362,6 +409,9 @@ def main():
     if not args.no_time_to_loss:
         print("bench: time to loss, BF16 + warm start against FP32", file=sys.stderr, flush=True)
         out["time_to_loss"] = bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w)
+    if not args.no_spmm:
+        print("bench: whitening SpMM on the document workload", file=sys.stderr, flush=True)
+        out["spmm"] = bench_spmm()
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1)

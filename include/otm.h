@@ -105,13 +105,16 @@ int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, double alph
  * columns sign-fixed so that each column's largest-magnitude entry is
  * positive (ties: lowest row).  W: d x k FP64; evals: k FP64 (s^2, the top
  * eigenvalues of the low-rank M2).  W_lo: optional (may be NULL) copy of W in
- * w_lo_dtype (OTM_F32 or OTM_BF16, round-to-nearest-even) for otm_whiten.
+ * w_lo_dtype (OTM_F32 or OTM_BF16, round-to-nearest-even) for otm_whiten,
+ * d x ldw_lo row-major (ldw_lo >= k; columns k..ldw_lo-1 written with 0;
+ * ignored when W_lo is NULL).  A row stride that is a multiple of 16 bytes
+ * lets otm_whiten gather W rows as 16-byte vectors.
  * info: device int32, 0 on success, 1 if sigma_k <= 1e-12 sigma_1 or
  * sigma_k <= 0 (OTM_ENOTPSD condition; W undefined).  k <= k_tilde <= 256. */
 size_t otm_whitener_workspace(int32_t d, int32_t k_tilde, int32_t k);
 int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, int32_t k,
-                 double* W, double* evals, void* W_lo, int w_lo_dtype, int32_t* info,
-                 void* ws, size_t ws_bytes, otm_stream stream);
+                 double* W, double* evals, void* W_lo, int w_lo_dtype, int32_t ldw_lo,
+                 int32_t* info, void* ws, size_t ws_bytes, otm_stream stream);
 
 /* Orthonormal basis of the sketch for power iterations (READING of Section
  * 4.2 for sampled data: the projected moment S^T M2 S is indefinite at
@@ -129,15 +132,19 @@ int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double* Q, int32_t
 
 /* ---- a3: whitening SpMM (Section 3.1 whitened data; Appendix A) ----------
  * Y[t, :] = r_t * sum_j C[t, j] W[j, :],  r_t = 1 / (row sum) if normalize
- * (document views) else 1.  W: n_cols x k row-major in w_dtype (OTM_F32 or
- * OTM_BF16).  Y: n_rows x ldy row-major in y_dtype (OTM_F32 or OTM_BF16,
+ * (document views) else 1.  W: n_cols x k in w_dtype (OTM_F32 or OTM_BF16),
+ * row-major with row stride ldw >= k elements; the padding columns k..ldw-1
+ * must be readable but do not change the result.  Rows are gathered as
+ * 16-byte vectors when ldw is a multiple of 16 bytes and W is 16-byte aligned
+ * (for instance ldw = k rounded up to 4 in FP32, to 8 in BF16), narrower ones
+ * otherwise; k <= 64 * vector width.  Y: n_rows x ldy row-major in y_dtype (OTM_F32 or OTM_BF16,
  * round-to-nearest-even), FP32 accumulation; columns k..ldy-1 are written
  * with 0.  ldy >= k; ldy % 8 == 0 for OTM_BF16, ldy % 4 == 0 for OTM_F32.
  * ybar: optional (NULL allowed) k floats, the mean of Y's rows computed from
  * the FP32 accumulators (Appendix A: ybar = E_t[y_t]), fixed-order sum.
  * A row with sum 0 under normalize gives a zero row. */
 size_t otm_whiten_workspace(int32_t n_rows, int32_t k);
-int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k,
+int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
                void* Y, int y_dtype, int32_t ldy, float* ybar,
                void* ws, size_t ws_bytes, otm_stream stream);
 

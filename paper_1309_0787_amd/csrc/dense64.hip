@@ -219,12 +219,19 @@ __global__ void colsign_kernel(const double* __restrict__ W, const double* __res
     sign[j] = (W[(size_t)bi * k + j] < 0.0) ? -1.0 : 1.0;
 }
 
+// W *= sign per column; W_lo (row stride ldw_lo, or ldw_lo = k when absent)
+// gets the rounded copy and zeros in its padding columns k..ldw_lo-1.
 __global__ void apply_sign_kernel(double* __restrict__ W, const double* __restrict__ sign, int d, int k,
-                                  void* __restrict__ W_lo, int lo_dtype) {
+                                  void* __restrict__ W_lo, int lo_dtype, int ldw_lo) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)d * k) return;
-    const double v = W[e] * sign[e % k];
-    W[e] = v;
+    if (e >= (int64_t)d * ldw_lo) return;
+    const int64_t row = e / ldw_lo;
+    const int col = static_cast<int>(e - row * ldw_lo);
+    double v = 0.0;
+    if (col < k) {
+        v = W[row * k + col] * sign[col];
+        W[row * k + col] = v;
+    }
     if (W_lo) {
         if (lo_dtype == OTM_F32) static_cast<float*>(W_lo)[e] = static_cast<float>(v);
         else static_cast<__bf16*>(W_lo)[e] = f32_to_bf16(static_cast<float>(v));
@@ -437,13 +444,14 @@ extern "C" size_t otm_whitener_workspace(int32_t d, int32_t k_tilde, int32_t k) 
 }
 
 extern "C" int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, int32_t k, double* W,
-                            double* evals, void* W_lo, int w_lo_dtype, int32_t* info, void* ws, size_t ws_bytes,
-                            otm_stream stream) {
+                            double* evals, void* W_lo, int w_lo_dtype, int32_t ldw_lo, int32_t* info, void* ws,
+                            size_t ws_bytes, otm_stream stream) {
     OTM_REQUIRE(O && S && W && evals && info, OTM_EINVAL, "O, S, W, evals, info must not be NULL");
     OTM_REQUIRE(d >= 1 && k >= 1 && k <= k_tilde && k_tilde <= kJacMaxN && k <= d, OTM_ESHAPE,
                 "need 1 <= k <= k_tilde <= 256 and k <= d");
     OTM_REQUIRE(W_lo == nullptr || w_lo_dtype == OTM_F32 || w_lo_dtype == OTM_BF16, OTM_EDTYPE,
                 "W_lo must be F32 or BF16");
+    OTM_REQUIRE(W_lo == nullptr || ldw_lo >= k, OTM_ESHAPE, "need ldw_lo >= k");
     OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whitener_workspace(d, k_tilde, k), OTM_EWORKSPACE,
                 "whitener workspace too small");
     hipStream_t s = as_stream(stream);
@@ -488,9 +496,10 @@ extern "C" int otm_whitener(const double* O, const double* S, int32_t d, int32_t
     if ((st = check_launch("colmax_partial_kernel")) != OTM_OK) return st;
     hipLaunchKernelGGL(colsign_kernel, dim3((k + 127) / 128), dim3(128), 0, s, W, pval, pidx, kSignBlocks, k, sgn);
     if ((st = check_launch("colsign_kernel")) != OTM_OK) return st;
-    const int64_t total = (int64_t)d * k;
+    const int ld_lo = W_lo ? ldw_lo : k;
+    const int64_t total = (int64_t)d * ld_lo;
     hipLaunchKernelGGL(apply_sign_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, sgn, d, k, W_lo,
-                       w_lo_dtype);
+                       w_lo_dtype, ld_lo);
     return check_launch("apply_sign_kernel");
 }
 

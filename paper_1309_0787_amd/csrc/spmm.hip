@@ -4,10 +4,16 @@
 //      Y[t, :] = r_t sum_j C[t, j] W[j, :]
 //    A group of LPR lanes owns one row; lane l of the group owns VPL
 //    consecutive columns of W and Y, so every stored entry of the row costs one
-//    coalesced gather of the W row (LPR*VPL*sizeof(W) bytes).  Column indices
-//    and values are loaded LPR at a time, one per lane, and broadcast within the
-//    group by shuffles; four W rows are in flight per iteration.  The group's
-//    FP32 accumulators also feed per-block column sums (fixed order) for ybar.
+//    coalesced gather of the W row.  The gathers come from L2 (W is reused by
+//    every row), and their cost is set by the number of load instructions and
+//    cache lines per entry, so W rows are read as 16-byte vectors when the row
+//    stride ldw allows it (ldw a multiple of the vector and >= k rounded up to
+//    it): a row of k = 50 FP32 values is 13 lanes of float4, four rows per
+//    wave.  Y is written with non-temporal stores (it is not read again here;
+//    W should stay in L2).  Column indices and values are loaded LPR at a time,
+//    one per lane, and broadcast within the group by shuffles; four W rows are
+//    in flight per iteration.  The group's FP32 accumulators also feed
+//    per-block column sums (fixed order) for ybar.
 //
 //  * FP64 passes of the second-moment operator (Section 2, Eq. 2moment;
 //    Section 4.2): T1 = diag(w2) C S, then C^T T1 together with C^T w2 and
@@ -23,7 +29,7 @@ namespace otm {
 namespace {
 
 constexpr int kSpmmThreads = 256;
-constexpr int kSpmmMaxBlocks = 2048;
+constexpr int kSpmmMaxBlocks = 8192;
 
 template <class T>
 __device__ __forceinline__ float to_f(T x) { return static_cast<float>(x); }
@@ -57,16 +63,17 @@ __device__ __forceinline__ void clamp_row(const int32_t* rowptr, int64_t nnz, in
     e = e < b ? b : (e > nnz ? nnz : e);
 }
 
-// Y = diag(r) C W ; per-block column sums of the FP32 rows into part[blockIdx][0..k)
-template <int VPL, class TW, class TY>
+// Y = diag(r) C W ; per-block column sums of the FP32 rows into part[0..k)[blockIdx]
+template <int VPL, int LPR, class TW, class TY>
 __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int normalize, const TW* __restrict__ W,
-                                                              int k, TY* __restrict__ Y, int ldy, int lpr,
+                                                              int k, int ldw, TY* __restrict__ Y, int ldy,
                                                               float* __restrict__ part) {
-    extern __shared__ float s_colsum[];   // [rows_per_block][lpr*VPL]
+    constexpr int lpr = LPR;
+    constexpr int rows_per_block = kSpmmThreads / LPR;
+    __shared__ float s_colsum[rows_per_block * LPR * VPL];
     const int tid = threadIdx.x;
-    const int g_lane = tid % lpr;          // lane within the row group
-    const int slot = tid / lpr;
-    const int rows_per_block = kSpmmThreads / lpr;
+    const int g_lane = tid % LPR;          // lane within the row group
+    const int slot = tid / LPR;
     const int col0 = g_lane * VPL;
     const bool active = col0 < k;
     float colacc[VPL];
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        if (active && c4[u] >= 0) load_w<VPL>(W + (size_t)c4[u] * k + col0, w4[u]);
+                        if (active && c4[u] >= 0) load_w<VPL>(W + (size_t)c4[u] * ldw + col0, w4[u]);
                         else {
 #pragma unroll
                             for (int v = 0; v < VPL; ++v) w4[u][v] = 0.f;
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
                     const int c = __shfl(my_col, jj, lpr);
                     const float val = __shfl(my_val, jj, lpr);
                     float w1[VPL];
-                    if (active && c >= 0) load_w<VPL>(W + (size_t)c * k + col0, w1);
+                    if (active && c >= 0) load_w<VPL>(W + (size_t)c * ldw + col0, w1);
                     else {
 #pragma unroll
                         for (int v = 0; v < VPL; ++v) w1[v] = 0.f;
@@ -136,14 +143,29 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
             const float r = normalize ? (rowsum > 0.f ? 1.0f / rowsum : 0.f) : 1.0f;
             TY* yrow = Y + (size_t)row * ldy;
             if (active) {
+                typedef TY YVec __attribute__((ext_vector_type(VPL)));
+                TY* dst = yrow + col0;
+                if (col0 + VPL <= k && reinterpret_cast<uintptr_t>(dst) % sizeof(YVec) == 0) {
+                    YVec y;
 #pragma unroll
-                for (int v = 0; v < VPL; ++v) {
-                    const float y = acc[v] * r;
-                    colacc[v] += y;
-                    yrow[col0 + v] = static_cast<TY>(y);
+                    for (int v = 0; v < VPL; ++v) {
+                        const float yv = acc[v] * r;
+                        colacc[v] += yv;
+                        y[v] = static_cast<TY>(yv);
+                    }
+                    __builtin_nontemporal_store(y, reinterpret_cast<YVec*>(dst));
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) {
+                        if (col0 + v < k) {      // the last lane's vector may reach into W's padding columns
+                            const float yv = acc[v] * r;
+                            colacc[v] += yv;
+                            __builtin_nontemporal_store(static_cast<TY>(yv), dst + v);
+                        }
+                    }
                 }
             }
-            for (int c = k + g_lane; c < ldy; c += lpr) yrow[c] = static_cast<TY>(0.0f);
+            for (int c = k + g_lane; c < ldy; c += lpr) __builtin_nontemporal_store(static_cast<TY>(0.0f), yrow + c);
         }
     }
     // block column sums in a fixed order: slots 0..rows_per_block-1
@@ -154,20 +176,30 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
     for (int c = tid; c < k; c += kSpmmThreads) {
         float s = 0.f;
         for (int sl = 0; sl < rows_per_block; ++sl) s += s_colsum[sl * width + c];
-        part[(size_t)blockIdx.x * k + c] = s;
+        part[(size_t)c * gridDim.x + blockIdx.x] = s;     // column-major: the finalize reads it coalesced
     }
 }
 
-// out[c] = scale * sum_b part[b][c], fixed order, FP64 accumulation
-// One workgroup per column: strided FP64 partial sums, then a fixed-order LDS
-// tree, so the mean does not depend on scheduling.
+// out[c] = scale * sum_b part[c][b], fixed order, FP64 accumulation
+// One workgroup per column: each thread sums its strided blocks in four
+// interleaved FP64 partials (independent loads in flight), then a fixed-order
+// LDS tree, so the mean does not depend on scheduling.
 constexpr int kFinThreads = 256;
 __global__ __launch_bounds__(kFinThreads) void colsum_finalize_kernel(const float* __restrict__ part, int nblocks,
                                                                       int k, double scale, float* __restrict__ out) {
     __shared__ double red[kFinThreads];
     const int c = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += part[(size_t)b * k + c];
+    const float* col = part + (size_t)c * nblocks;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = threadIdx.x;
+    for (; b + 3 * kFinThreads < nblocks; b += 4 * kFinThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s4[u] += col[b + u * kFinThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u)          // at most three strided blocks remain
+        if (b + u * kFinThreads < nblocks) s4[u] += col[b + u * kFinThreads];
+    double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = kFinThreads / 2; h > 0; h >>= 1) {
@@ -177,24 +209,37 @@ __global__ __launch_bounds__(kFinThreads) void colsum_finalize_kernel(const floa
     if (threadIdx.x == 0) out[c] = static_cast<float>(red[0] * scale);
 }
 
-template <int VPL, class TW, class TY>
-int launch_whiten(const otm_csr& C, int normalize, const void* W, int k, void* Y, int ldy, float* part,
-                  int nblocks, int lpr, hipStream_t st) {
-    const size_t shm = sizeof(float) * (kSpmmThreads / lpr) * lpr * VPL;
-    hipLaunchKernelGGL((whiten_kernel<VPL, TW, TY>), dim3(nblocks), dim3(kSpmmThreads), shm, st, C, normalize,
-                       static_cast<const TW*>(W), k, static_cast<TY*>(Y), ldy, lpr, part);
+template <int VPL, int LPR, class TW, class TY>
+int launch_whiten(const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy, float* part,
+                  int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((whiten_kernel<VPL, LPR, TW, TY>), dim3(nblocks), dim3(kSpmmThreads), 0, st, C, normalize,
+                       static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part);
     return check_launch("whiten_kernel");
 }
 
+template <int VPL, class TW, class TY>
+int dispatch_lpr(int lpr, const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy,
+                 float* part, int nblocks, hipStream_t st) {
+    switch (lpr) {
+        case 2: return launch_whiten<VPL, 2, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 4: return launch_whiten<VPL, 4, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 8: return launch_whiten<VPL, 8, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 16: return launch_whiten<VPL, 16, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 32: return launch_whiten<VPL, 32, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 64: return launch_whiten<VPL, 64, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        default: return fail(OTM_EINVAL, "bad lanes per row");
+    }
+}
+
 template <class TW, class TY>
-int dispatch_whiten(int vpl, const otm_csr& C, int normalize, const void* W, int k, void* Y, int ldy, float* part,
-                    int nblocks, int lpr, hipStream_t st) {
+int dispatch_whiten(int vpl, const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy,
+                    float* part, int nblocks, int lpr, hipStream_t st) {
     switch (vpl) {
-        case 1: return launch_whiten<1, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
-        case 2: return launch_whiten<2, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
-        case 4: return launch_whiten<4, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+        case 1: return dispatch_lpr<1, TW, TY>(lpr, C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 2: return dispatch_lpr<2, TW, TY>(lpr, C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 4: return dispatch_lpr<4, TW, TY>(lpr, C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
         default:
-            if constexpr (sizeof(TW) == 2) return launch_whiten<8, TW, TY>(C, normalize, W, k, Y, ldy, part, nblocks, lpr, st);
+            if constexpr (sizeof(TW) == 2) return dispatch_lpr<8, TW, TY>(lpr, C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
             return fail(OTM_EINVAL, "bad vector width");
     }
 }
@@ -203,12 +248,17 @@ struct WhitenPlan {
     int vpl, lpr, nblocks;
 };
 
-WhitenPlan plan_whiten(int32_t n_rows, int k, int w_dtype) {
+// Widest vector (at most 16 bytes) that the row stride, the base alignment and
+// the row length allow: ldw % vpl == 0, W aligned to the vector, and the last
+// lane's vector (up to k rounded up to vpl) inside the row.
+WhitenPlan plan_whiten(int32_t n_rows, int k, int ldw, int w_dtype, uintptr_t w_addr) {
     WhitenPlan p{};
-    const int vmax = (w_dtype == OTM_BF16) ? 8 : 4;
+    const int esize = (w_dtype == OTM_BF16) ? 2 : 4;
     p.vpl = 1;
-    for (int v = vmax; v > 1; v >>= 1)
-        if (k % v == 0) { p.vpl = v; break; }
+    for (int v = 16 / esize; v > 1; v >>= 1) {
+        const int span = (k + v - 1) / v * v;
+        if (ldw % v == 0 && span <= ldw && w_addr % (uintptr_t)(v * esize) == 0) { p.vpl = v; break; }
+    }
     const int lanes = (k + p.vpl - 1) / p.vpl;
     p.lpr = 1;
     while (p.lpr < lanes) p.lpr <<= 1;
@@ -353,23 +403,25 @@ using namespace otm;
 
 extern "C" size_t otm_whiten_workspace(int32_t n_rows, int32_t k) {
     if (n_rows < 0 || k < 1) return 0;
-    const WhitenPlan p = plan_whiten(n_rows, k, OTM_BF16);
-    const WhitenPlan q = plan_whiten(n_rows, k, OTM_F32);
-    const int nb = p.nblocks > q.nblocks ? p.nblocks : q.nblocks;
+    // every plan has at least kSpmmThreads / 64 rows per block
+    int64_t nb = ((int64_t)n_rows + 3) / 4;
+    if (nb > kSpmmMaxBlocks) nb = kSpmmMaxBlocks;
+    if (nb < 1) nb = 1;
     return ws_round(sizeof(float) * (size_t)nb * k);
 }
 
-extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, void* Y,
-                          int y_dtype, int32_t ldy, float* ybar, void* ws, size_t ws_bytes, otm_stream stream) {
+extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
+                          void* Y, int y_dtype, int32_t ldy, float* ybar, void* ws, size_t ws_bytes,
+                          otm_stream stream) {
     int st = validate_csr_header(C, "C");
     if (st != OTM_OK) return st;
     OTM_REQUIRE(W != nullptr && (Y != nullptr || C->n_rows == 0), OTM_EINVAL, "W and Y must not be NULL");
-    OTM_REQUIRE(k >= 1 && ldy >= k, OTM_ESHAPE, "need k >= 1 and ldy >= k");
+    OTM_REQUIRE(k >= 1 && ldy >= k && ldw >= k, OTM_ESHAPE, "need k >= 1, ldw >= k and ldy >= k");
     OTM_REQUIRE(w_dtype == OTM_F32 || w_dtype == OTM_BF16, OTM_EDTYPE, "W must be F32 or BF16");
     OTM_REQUIRE(y_dtype == OTM_F32 || y_dtype == OTM_BF16, OTM_EDTYPE, "Y must be F32 or BF16");
     OTM_REQUIRE(y_dtype != OTM_BF16 || ldy % 8 == 0, OTM_ESHAPE, "BF16 Y needs ldy % 8 == 0");
     OTM_REQUIRE(y_dtype != OTM_F32 || ldy % 4 == 0, OTM_ESHAPE, "F32 Y needs ldy % 4 == 0");
-    const WhitenPlan p = plan_whiten(C->n_rows, k, w_dtype);
+    const WhitenPlan p = plan_whiten(C->n_rows, k, ldw, w_dtype, reinterpret_cast<uintptr_t>(W));
     OTM_REQUIRE(p.lpr <= 64, OTM_ECAPACITY, "k too large for the whitening kernel (k <= 64 * vector width)");
     OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whiten_workspace(C->n_rows, k), OTM_EWORKSPACE,
                 "whiten workspace too small");
@@ -383,11 +435,13 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
     hipStream_t s = as_stream(stream);
     float* part = static_cast<float*>(ws);
     if (w_dtype == OTM_F32) {
-        st = (y_dtype == OTM_F32) ? dispatch_whiten<float, float>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s)
-                                  : dispatch_whiten<float, __bf16>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s);
+        st = (y_dtype == OTM_F32)
+                 ? dispatch_whiten<float, float>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s)
+                 : dispatch_whiten<float, __bf16>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s);
     } else {
-        st = (y_dtype == OTM_F32) ? dispatch_whiten<__bf16, float>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s)
-                                  : dispatch_whiten<__bf16, __bf16>(p.vpl, *C, normalize, W, k, Y, ldy, part, p.nblocks, p.lpr, s);
+        st = (y_dtype == OTM_F32)
+                 ? dispatch_whiten<__bf16, float>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s)
+                 : dispatch_whiten<__bf16, __bf16>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s);
     }
     if (st != OTM_OK) return st;
     if (ybar) {

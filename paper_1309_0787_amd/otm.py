@@ -70,12 +70,13 @@ _SIGS = {
     "otm_m2_apply": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), ctypes.c_int, _dbl, _vp, _i32,
                                     _vp, _vp, _vp, _sz, _vp]),
     "otm_whitener_workspace": (_sz, [_i32, _i32, _i32]),
-    "otm_whitener": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "otm_whitener": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _i32, _vp, _vp, _sz,
+                                    _vp]),
     "otm_orthonormalize_workspace": (_sz, [_i32, _i32]),
     "otm_orthonormalize": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "otm_whiten_workspace": (_sz, [_i32, _i32]),
-    "otm_whiten": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _vp, ctypes.c_int,
-                                  _i32, _vp, _vp, _sz, _vp]),
+    "otm_whiten": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _i32, _vp,
+                                  ctypes.c_int, _i32, _vp, _vp, _sz, _vp]),
     "otm_sgd_step": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "otm_sgd_run": (ctypes.c_int, [ctypes.POINTER(_SgdParams), _i32, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i64,
                                    _i64, _vp, _vp, _vp, _vp, _vp]),
@@ -157,6 +158,16 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _ptr_rows(t) -> tuple[int, int]:
+    """(pointer, row stride) of a 2-D GPU tensor with unit column stride (a
+    row-padded buffer or a column slice of one)."""
+    if not t.is_cuda:
+        raise OtmError(-1, "tensor must live on the GPU")
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise OtmError(-1, "matrix must be row-major with unit column stride")
+    return t.data_ptr(), t.stride(0)
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -213,20 +224,32 @@ def m2_apply(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: tor
     return O
 
 
-def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = F32, stream=None):
-    """(W FP64 d x k, evals FP64 k, W_lo in w_lo_dtype or None).  Raises OtmNotPSD."""
+def default_ldw(k: int, dtype: int) -> int:
+    """Row stride of W for the whitening SpMM: k rounded up to 16 bytes."""
+    per = 8 if dtype == BF16 else 4
+    return (k + per - 1) // per * per
+
+
+def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = F32, ldw_lo: int | None = None,
+             stream=None):
+    """(W FP64 d x k, evals FP64 k, W_lo in w_lo_dtype or None).  W_lo is the
+    d x k view of a d x ldw_lo buffer (default: k rounded up to 16 bytes) whose
+    padding columns hold 0.  Raises OtmNotPSD."""
     d, kt = O.shape
     W = torch.empty((d, k), dtype=torch.float64, device=O.device)
     ev = torch.empty(k, dtype=torch.float64, device=O.device)
-    W_lo = None if w_lo_dtype is None else torch.empty((d, k), dtype=_TORCH_DTYPE[w_lo_dtype], device=O.device)
+    W_lo, ld = None, k
+    if w_lo_dtype is not None:
+        ld = default_ldw(k, w_lo_dtype) if ldw_lo is None else int(ldw_lo)
+        W_lo = torch.empty((d, ld), dtype=_TORCH_DTYPE[w_lo_dtype], device=O.device)
     info = torch.zeros(1, dtype=torch.int32, device=O.device)
     ws = _ws(lib().otm_whitener_workspace(d, kt, k), O.device)
     _check(lib().otm_whitener(_ptr(O), _ptr(S), d, kt, k, _ptr(W), _ptr(ev), _ptr(W_lo),
-                              F32 if w_lo_dtype is None else w_lo_dtype, _ptr(info), _ptr(ws), ws.numel(),
+                              F32 if w_lo_dtype is None else w_lo_dtype, ld, _ptr(info), _ptr(ws), ws.numel(),
                               _stream(stream)))
     if int(info.item()) != 0:
         raise OtmNotPSD(-4, "projected second moment has no k positive eigenvalues")
-    return W, ev, W_lo
+    return W, ev, (None if W_lo is None else W_lo[:, :k])
 
 
 def orthonormalize(Y: torch.Tensor, stream=None) -> torch.Tensor:
@@ -258,15 +281,17 @@ def default_ldy(k: int) -> int:
 
 def whiten(C: DeviceCSR, normalize: bool, W: torch.Tensor, y_dtype: int = F32, ldy: int | None = None,
            want_ybar: bool = True, out: torch.Tensor | None = None, stream=None):
-    """Y (n x ldy, y_dtype) and ybar (k FP32, or None)."""
+    """Y (n x ldy, y_dtype) and ybar (k FP32, or None).  W (d x k) may be a
+    column slice of a row-padded buffer; its row stride is passed as ldw."""
     d, k = W.shape
+    w_ptr, ldw = _ptr_rows(W)
     ldy = default_ldy(k) if ldy is None else ldy
     Y = out if out is not None else torch.empty((C.n_rows, ldy), dtype=_TORCH_DTYPE[y_dtype], device=W.device)
     ybar = torch.empty(k, dtype=torch.float32, device=W.device) if want_ybar else None
     ws = _ws(lib().otm_whiten_workspace(C.n_rows, k), W.device)
     cc = C.c()
-    _check(lib().otm_whiten(ctypes.byref(cc), int(normalize), _ptr(W), _DTYPE_CODE[W.dtype], k, _ptr(Y), y_dtype,
-                            ldy, _ptr(ybar), _ptr(ws), ws.numel(), _stream(stream)))
+    _check(lib().otm_whiten(ctypes.byref(cc), int(normalize), w_ptr, _DTYPE_CODE[W.dtype], k, ldw, _ptr(Y),
+                            y_dtype, ldy, _ptr(ybar), _ptr(ws), ws.numel(), _stream(stream)))
     return Y, ybar
 
 

@@ -60,6 +60,9 @@ def test_whitener_exact_rank_k(d, k, kt):
     assert rel(Wg, Wref) < 1e-9
     np.testing.assert_allclose(host(ev), evref, rtol=1e-10)
     np.testing.assert_array_equal(host(Wlo), torch.as_tensor(Wg).to(torch.bfloat16).double().numpy())
+    ld = Wlo.stride(0)                              # the row-padded buffer behind the view: zeros in the padding
+    assert ld == otm.default_ldw(k, otm.BF16)
+    assert np.all(host(Wlo.as_strided((d, ld), (ld, 1)))[:, k:] == 0.0)
 
 
 def test_whitener_sampled_graph():
@@ -73,6 +76,11 @@ def test_whitener_sampled_graph():
     assert rel(host(W), Wref) < 1e-9
     np.testing.assert_allclose(host(ev), evref, rtol=1e-10)
     np.testing.assert_array_equal(host(Wlo), f32_round(host(W)))
+    _, _, Wlo2 = otm.whitener(to_dev(O, torch.float64), to_dev(Q, torch.float64), 10, w_lo_dtype=otm.F32, ldw_lo=13)
+    torch.cuda.synchronize()
+    assert Wlo2.stride(0) == 13
+    np.testing.assert_array_equal(host(Wlo2), host(Wlo))
+    assert np.all(host(Wlo2.as_strided((Wlo2.shape[0], 13), (13, 1)))[:, 10:] == 0.0)
 
 
 @pytest.mark.parametrize("normalize", [False, True])

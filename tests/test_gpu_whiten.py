@@ -54,6 +54,49 @@ def test_whiten_document_views_normalised(k):
         np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
 
 
+@pytest.mark.parametrize("k", [3, 10, 50, 100, 129, 200])
+@pytest.mark.parametrize("w_dt,y_dt", [(otm.F32, otm.F32), (otm.BF16, otm.BF16), (otm.BF16, otm.F32)])
+def test_whiten_padded_row_stride(k, w_dt, y_dt):
+    """W as the d x k slice of a row-padded buffer whose padding holds NaN (the
+    16-byte vector gathers read it; it must not reach Y or ybar), and as a
+    slice that starts one column in (unaligned: narrower gathers)."""
+    g = synth.mmsb(n=1500, k=4, alpha0=0.3, p=0.2, q=0.02, n_x=900, seed=k + 1)
+    W = synth.projection(g.C.n_cols, k, seed=4)
+    Wr = bf16_round(W) if w_dt == otm.BF16 else f32_round(W)
+    tdt = torch.bfloat16 if w_dt == otm.BF16 else torch.float32
+    ldw = otm.default_ldw(k, w_dt)
+    for off, ld in ((0, ldw), (1, ldw + 8)):
+        buf = torch.full((g.C.n_cols, ld), float("nan"), dtype=tdt, device=dev())
+        buf[:, off:off + k] = to_dev(Wr, tdt)
+        if off and k > 64:                          # one element per lane: k <= 64
+            with pytest.raises(otm.OtmError) as e:
+                otm.whiten(csr_dev(g.C), False, buf[:, off:off + k], y_dtype=y_dt)
+            assert e.value.status == -8
+            continue
+        Y, ybar = otm.whiten(csr_dev(g.C), False, buf[:, off:off + k], y_dtype=y_dt)
+        torch.cuda.synchronize()
+        Yref, ybref = oracle.whiten(g.C, Wr, normalize=False)
+        Yg = host(Y)
+        _check_rows(Yg, Yref, k, 2e-6 if y_dt == otm.F32 else 2.0 ** -8)
+        assert np.all(Yg[:, k:] == 0.0)
+        np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
+
+
+def test_whiten_document_views_padded_stride():
+    """The document-workload shape (k = 50 FP32, W padded to 52 columns)."""
+    inst = synth.lda(d=3000, k=5, alpha0=1.0, beta=0.1, n_docs=3001, mean_len=60.0, seed=11)
+    k = 50
+    W = f32_round(synth.projection(3000, k, seed=6))
+    buf = torch.full((3000, otm.default_ldw(k, otm.F32)), float("nan"), dtype=torch.float32, device=dev())
+    buf[:, :k] = to_dev(W)
+    for v in inst.views:
+        Y, ybar = otm.whiten(csr_dev(v), True, buf[:, :k], y_dtype=otm.F32)
+        torch.cuda.synchronize()
+        Yref, ybref = oracle.whiten(v, W, normalize=True)
+        _check_rows(host(Y), Yref, k, 2e-6)
+        np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
+
+
 def test_whiten_empty_rows_and_empty_matrix():
     # rows 0, 3 and the last are empty
     rowptr = np.array([0, 0, 2, 3, 3, 5, 5], dtype=np.int32)
