@@ -17,6 +17,7 @@
 // (layout 0) or, layout 1, 8 x 1 for KP <= 32 and 2 x 4 above; batch staging
 // for one aliased view or three views.
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -31,7 +32,7 @@ namespace {
 
 constexpr int kClasses = kMaxK / 16;          // KP = 16 (c + 1)
 constexpr int kVariants = kClasses * 2 * 2;   // x layout x view staging
-constexpr int kMaxBranches = 4;               // concurrent streams of one run (hardware queues)
+constexpr int kMaxBranches = 16;              // most concurrent streams of one run (hardware queues)
 
 __host__ __device__ constexpr int variant_id(int cls, int layout, int three_views) {
     return (cls * 2 + layout) * 2 + three_views;
@@ -144,6 +145,17 @@ int per_cu(int v, int* out) {
 // (default priority, non-blocking streams; events without timing), created
 // once per device and kept until the process ends.  Runs on one device must
 // not be issued from several host threads at once.
+// Kernels of one process run side by side on at most as many hardware queues
+// as the HIP runtime gives it (GPU_MAX_HW_QUEUES, 4 by default).
+int hw_queues() {
+    static const int q = [] {
+        const char* v = getenv("GPU_MAX_HW_QUEUES");
+        const int n = v ? atoi(v) : 4;
+        return n < 1 ? 1 : (n > kMaxBranches ? kMaxBranches : n);
+    }();
+    return q;
+}
+
 struct Branches {
     hipStream_t stream[kMaxBranches];
     hipEvent_t fork;
@@ -159,7 +171,7 @@ int branches(Branches** out) {
     OTM_REQUIRE(dev >= 0 && dev < 64, OTM_EINVAL, "device index out of range");
     Branches& b = per_dev[dev];
     if (!b.ready) {
-        for (int i = 0; i < kMaxBranches; ++i) {
+        for (int i = 0; i < hw_queues(); ++i) {
             if ((e = hipStreamCreateWithFlags(&b.stream[i], hipStreamNonBlocking)) != hipSuccess)
                 return hip_fail(e, "hipStreamCreateWithFlags");
             if ((e = hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming)) != hipSuccess)
@@ -268,7 +280,11 @@ int enqueue_plan(const otm_plan_s& P, const void* image, int32_t* counters, hipS
     // first, and run one after another there; each kernel takes its branch's
     // share of the device (its variant's resident workgroups over the number
     // of branches, at most its job count).
-    const int nb = std::min(ng, kMaxBranches);
+    const int nb = std::min(ng, hw_queues());
+    // every group on a branch of its own: all start at once and each kernel may
+    // take the whole device (the dispatcher shares the CUs as queues drain);
+    // otherwise the groups of a branch run one after another on its share
+    const bool own = nb == ng;
     std::vector<int> order(ng), branch_of(ng), grid(ng);
     for (int i = 0; i < ng; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -280,7 +296,7 @@ int enqueue_plan(const otm_plan_s& P, const void* image, int32_t* counters, hipS
         load[b] += P.groups[i].work;
         int pc = 1;
         if ((s = per_cu(P.groups[i].variant, &pc)) != OTM_OK) return s;
-        const int want = (cus * pc + nb - 1) / nb;
+        const int want = own ? cus * pc : (cus * pc + nb - 1) / nb;
         grid[i] = std::max(1, std::min(P.groups[i].count, want));
     }
     const BatchJob* jobs = static_cast<const BatchJob*>(image);
