@@ -75,8 +75,8 @@ struct MmaF32 {
     __device__ static Frag yrow(const Y* row, int a0, int k) {
         return (row != nullptr && a0 < k) ? row[a0] : 0.0f;
     }
-    __device__ static Chunk load_chunk(const Y* p, int valid) {
-        Chunk v = *reinterpret_cast<const Chunk*>(p);
+    // elements e >= valid of a row piece set to 0 (the padding past k)
+    __device__ static Chunk mask_chunk(Chunk v, int valid) {
 #pragma unroll
         for (int e = 0; e < CH; ++e)
             if (e >= valid) v[e] = 0.0f;
@@ -120,8 +120,7 @@ struct MmaBF16 {
         }
         return zero_frag();
     }
-    __device__ static Chunk load_chunk(const Y* p, int valid) {
-        Chunk v = *reinterpret_cast<const Chunk*>(p);
+    __device__ static Chunk mask_chunk(Chunk v, int valid) {
 #pragma unroll
         for (int e = 0; e < CH; ++e)
             if (e >= valid) v[e] = f32_to_bf16(0.0f);
@@ -277,8 +276,11 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
     for (int tj = 0; tj < TC; ++tj) live[tj] = ((wc + WC * tj) * 16 + l16 < k) ? 1.0f : 0.0f;
 
-    // ---- batch prefetch state (NSTAGE > 0)
+    // ---- batch prefetch state (NSTAGE > 0).  Row indices run two steps ahead
+    // of the rows (their load has a whole step to arrive) and are checked only
+    // where the rows are loaded, so no load waits right after it is issued.
     int32_t pidx[NCH];
+    uint32_t plive = 0;                 // bit j: chunk j belongs to a row of the batch
     typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
     // steps t >= end_step (up to t_end) are the scoring pass: rows in natural order
     const int t_end = g.end_step + ((SCORE && g.score != nullptr) ? g.spp : 0);
@@ -290,17 +292,15 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             const int row0 = train ? (t - pass * g.spp) * B : (live_step ? (t - g.end_step) * B : 0);
             const int nb = live_step ? min(B, n - row0) : 0;
             const int32_t* pp = (train && perms) ? perms + (size_t)pass * n + row0 : nullptr;
+            plive = 0;
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
                 const int tr = c / cpr;
-                int32_t r = -1;
+                int32_t r = 0;
                 if (c < MB * cpr && tr < nb) {
                     r = pp ? pp[tr] : row0 + tr;
-                    if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
-                        r = 0;
-                        bad = true;
-                    }
+                    plive |= 1u << j;
                 }
                 pidx[j] = r;
             }
@@ -312,11 +312,19 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
                 const int a0 = (c % cpr) * M::CH;
+                const bool live_c = (plive >> j) & 1u;
+                int32_t r = pidx[j];
+                if (live_c && (r < 0 || r >= n)) {   // out-of-range permutation entry: reads row 0, reported
+                    r = 0;
+                    bad = true;
+                }
+                // the columns past k of a row's last chunk are cleared at commit,
+                // so nothing here waits for the load
 #pragma unroll
                 for (int v = 0; v < NSTAGE; ++v)
-                    pbuf[v][j] = (pidx[j] >= 0 && a0 < k)
-                                     ? M::load_chunk(Yv[v] + (size_t)pidx[j] * ldy + a0, k - a0)
-                                     : M::zero_chunk();
+                    pbuf[v][j] = (live_c && a0 < k) ? *reinterpret_cast<const typename M::Chunk*>(
+                                                          Yv[v] + (size_t)r * ldy + a0)
+                                                    : M::zero_chunk();
             }
         }
     };
@@ -329,13 +337,26 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     const int tr = c / cpr, a0 = (c % cpr) * M::CH;
 #pragma unroll
                     for (int v = 0; v < NSTAGE; ++v)
-                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * MB + tr) * SY + a0]) = pbuf[v][j];
+                        *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * MB + tr) * SY + a0]) =
+                            M::mask_chunk(pbuf[v][j], k - a0);
                 }
             }
         }
     };
     issue_index(g.start_step);
     issue_data();
+    issue_index(g.start_step + 1);
+    // NSTAGE == 0: this thread's row index of the next step (thread tr < MB holds row tr)
+    auto next_row = [&](int tn) -> int32_t {
+        const bool tr_train = !SCORE || tn < g.end_step;
+        const int tpass = tr_train ? tn / g.spp : 0;
+        const int ts = tr_train ? tn - tpass * g.spp : tn - g.end_step;
+        const int trow0 = ts * B;
+        if (tn >= t_end || tid >= min(B, n - trow0)) return 0;
+        return (tr_train && perms) ? perms[(size_t)tpass * n + trow0 + tid] : trow0 + tid;
+    };
+    int32_t nrow = 0;
+    if constexpr (NSTAGE == 0) nrow = next_row(g.start_step);
     __syncthreads();
 
     double score_g = 0.0, score_t = 0.0;   // scoring pass: sum G^3 and sum T(phi, phi, phi), per lane
@@ -349,11 +370,10 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 
         // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
         commit();
-        issue_index(t + 1);
         if constexpr (NSTAGE == 0) {
             if (tid < nb) {
-                int32_t r = (train && perms) ? perms[(size_t)pass * n + row0 + tid] : row0 + tid;
-                if (r < 0 || r >= n) {
+                int32_t r = nrow;
+                if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
                     r = 0;
                     bad = true;
                 }
@@ -507,8 +527,11 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         }
         __syncthreads();   // every read of G*G is done: the buffer takes Q next
 
-        // rows of step t+1 start their trip from global memory now
+        // rows of step t+1 start their trip from global memory now, then the
+        // row indices of step t+2
         issue_data();
+        issue_index(t + 2);
+        if constexpr (NSTAGE == 0) nrow = next_row(t + 1);
 
         // ================= phase 3: PA, PB one tile row at a time -> Q into the
         // exchange buffer (buf[i*SB + t] = Q[t][i]) and column sums of H
