@@ -94,7 +94,9 @@ struct MmaBF16 {
     using Chunk = bf16x8;
     static constexpr int KI = 32;
     static constexpr int EPL = 8;
-    static constexpr int SPAD = 8;
+    // LDS row padding: rows 288 bytes apart, 8 banks of shift per row (4 or
+    // 12 banks measured about 4% slower per step at k = 128)
+    static constexpr int SPAD = 16;
     static constexpr int CH = 8;
     static constexpr bool kPhiT = true;
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
@@ -281,6 +283,10 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     // where the rows are loaded, so no load waits right after it is issued.
     int32_t pidx[NCH];
     uint32_t plive = 0;                 // bit j: chunk j belongs to a row of the batch
+    bool pperm = false;                 // the rows come from the permutation (else row0 + tr)
+    int prow0 = 0;
+    // (a loaded index is only ever read where the rows are loaded: selecting
+    // between it and anything else right after the load would wait for it)
     typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
     // steps t >= end_step (up to t_end) are the scoring pass: rows in natural order
     const int t_end = g.end_step + ((SCORE && g.score != nullptr) ? g.spp : 0);
@@ -293,16 +299,16 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             const int nb = live_step ? min(B, n - row0) : 0;
             const int32_t* pp = (train && perms) ? perms + (size_t)pass * n + row0 : nullptr;
             plive = 0;
+            pperm = pp != nullptr;
+            prow0 = row0;
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
                 const int tr = c / cpr;
-                int32_t r = 0;
                 if (c < MB * cpr && tr < nb) {
-                    r = pp ? pp[tr] : row0 + tr;
+                    if (pp) pidx[j] = pp[tr];
                     plive |= 1u << j;
                 }
-                pidx[j] = r;
             }
         }
     };
@@ -313,7 +319,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 const int c = tid + j * kThreads;
                 const int a0 = (c % cpr) * M::CH;
                 const bool live_c = (plive >> j) & 1u;
-                int32_t r = pidx[j];
+                int32_t r = pperm ? pidx[j] : prow0 + c / cpr;
                 if (live_c && (r < 0 || r >= n)) {   // out-of-range permutation entry: reads row 0, reported
                     r = 0;
                     bad = true;
@@ -346,17 +352,20 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     issue_index(g.start_step);
     issue_data();
     issue_index(g.start_step + 1);
-    // NSTAGE == 0: this thread's row index of the next step (thread tr < MB holds row tr)
-    auto next_row = [&](int tn) -> int32_t {
+    // NSTAGE == 0: this thread's row index of the next step (thread tr < MB holds
+    // row tr), loaded a step ahead: nperm says whether nrow holds it (else the
+    // step's rows are in natural order)
+    int32_t nrow = 0;
+    bool nperm = false;
+    auto next_row = [&](int tn) {
         const bool tr_train = !SCORE || tn < g.end_step;
         const int tpass = tr_train ? tn / g.spp : 0;
         const int ts = tr_train ? tn - tpass * g.spp : tn - g.end_step;
         const int trow0 = ts * B;
-        if (tn >= t_end || tid >= min(B, n - trow0)) return 0;
-        return (tr_train && perms) ? perms[(size_t)tpass * n + trow0 + tid] : trow0 + tid;
+        nperm = tr_train && perms != nullptr;
+        if (nperm && tn < t_end && tid < min(B, n - trow0)) nrow = perms[(size_t)tpass * n + trow0 + tid];
     };
-    int32_t nrow = 0;
-    if constexpr (NSTAGE == 0) nrow = next_row(g.start_step);
+    if constexpr (NSTAGE == 0) next_row(g.start_step);
     __syncthreads();
 
     double score_g = 0.0, score_t = 0.0;   // scoring pass: sum G^3 and sum T(phi, phi, phi), per lane
@@ -372,7 +381,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         commit();
         if constexpr (NSTAGE == 0) {
             if (tid < nb) {
-                int32_t r = nrow;
+                int32_t r = nperm ? nrow : row0 + tid;
                 if (r < 0 || r >= n) {   // out-of-range permutation entry: reads row 0, reported
                     r = 0;
                     bad = true;
@@ -531,7 +540,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         // row indices of step t+2
         issue_data();
         issue_index(t + 2);
-        if constexpr (NSTAGE == 0) nrow = next_row(t + 1);
+        if constexpr (NSTAGE == 0) next_row(t + 1);
 
         // ================= phase 3: PA, PB one tile row at a time -> Q into the
         // exchange buffer (buf[i*SB + t] = Q[t][i]) and column sums of H
