@@ -102,6 +102,28 @@ def test_batched_equals_single_runs_and_scores():
         assert int(run.best[i].item()) == int(np.argmin(got))
 
 
+def test_batched_same_result_with_every_group_on_its_own_queue(tmp_path):
+    """With 16 hardware queues every variant group gets a branch of its own and
+    a whole-device grid; the jobs' arithmetic does not depend on scheduling, so
+    the factors and scores equal (bit for bit) those of the default 4 queues
+    (groups sharing branches).  The 16-queue run is a child process: the queue
+    count is fixed when the HIP runtime starts."""
+    import subprocess
+    import sys
+    restarts = 3
+    problems = [_problem(n, k, seed=100 + i, three=t, restarts=restarts) for i, (n, k, t) in enumerate(SHAPES)]
+    _, run = _run_batched(problems, restarts)
+    out = tmp_path / "child.npz"
+    env = dict(os.environ, GPU_MAX_HW_QUEUES="16")
+    child = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batched_child.py")
+    r = subprocess.run([sys.executable, child, str(out)], env=env, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    got = np.load(out)
+    for i in range(len(problems)):
+        np.testing.assert_array_equal(got[f"phi{i}"], run.Phi[i].cpu().numpy())
+        np.testing.assert_array_equal(got[f"score{i}"], run.scores[i].cpu().numpy())
+
+
 def test_batched_vs_oracle_runs_both_layouts(tmp_path):
     restarts = 2
     problems = [_problem(n, k, seed=200 + i, three=t, restarts=restarts)
