@@ -7,7 +7,8 @@
 // every 2x2 block (rows of pair P, columns of pair Q) becomes R_P^T X R_Q with
 // R = [[c, s], [-s, c]].  A pair is rotated only while
 // |a_pq| > 1e-15 sqrt(|a_pp a_qq|) and |a_pq| > 1e-15 ||A||_F; the sweeps
-// stop after one without any rotation (at most 60).
+// stop once no pair passes that test (checked for all pairs at once after
+// each sweep, so the last, rotation-free sweep is not run; at most 60).
 //
 // n <= 200: the matrix lives in LDS as a packed upper triangle (20100
 // doubles), so a round never leaves the CU, and every round's rotations are
@@ -148,6 +149,21 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
             __syncthreads();
         }
         done_rounds += N - 1;
+        if (!s_rotated) break;
+        // converged when no pair passes the rotation test: the next sweep
+        // would leave A as it is, so it is not run
+        __syncthreads();
+        if (tid == 0) s_rotated = 0;
+        __syncthreads();
+        for (int e = tid; e < n * n; e += kJacThreads) {
+            const int i = e / n, j = e - (e / n) * n;
+            if (i < j) {
+                const double aij = sA[tri_idx(i, j, n)];
+                const double aii = sA[tri_idx(i, i, n)], ajj = sA[tri_idx(j, j, n)];
+                if (!(fabs(aij) <= 1e-15 * sqrt(fabs(aii * ajj)) || fabs(aij) <= abs_tol)) s_rotated = 1;
+            }
+        }
+        __syncthreads();
         if (!s_rotated) break;
         __syncthreads();
     }
@@ -292,6 +308,20 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_global_kernel(double* __re
             __threadfence_block();
             __syncthreads();
         }
+        if (!s_rotated) break;
+        // converged when no pair passes the rotation test (see the LDS form)
+        __syncthreads();
+        if (tid == 0) s_rotated = 0;
+        __syncthreads();
+        for (int e = tid; e < n * n; e += kJacThreads) {
+            const int i = e / n, j = e - (e / n) * n;
+            if (i < j) {
+                const double aij = A[(size_t)i * n + j];
+                const double aii = A[(size_t)i * n + i], ajj = A[(size_t)j * n + j];
+                if (!(fabs(aij) <= 1e-15 * sqrt(fabs(aii * ajj)) || fabs(aij) <= abs_tol)) s_rotated = 1;
+            }
+        }
+        __syncthreads();
         if (!s_rotated) break;
         __syncthreads();
     }
