@@ -276,6 +276,7 @@ WhitenPlan plan_whiten(int32_t n_rows, int k, int ldw, int w_dtype, uintptr_t w_
 // m <= 256 columns (lane, lane+64, ...).
 // ---------------------------------------------------------------------------
 constexpr int kM2Threads = 256;
+constexpr int kM2Unroll = 4;
 
 // T1[t,:] = w2_t sum_j C[t,j] S[j,:]; w1[t], w2[t] from the row sum when normalize
 __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int normalize, const double* __restrict__ S,
@@ -289,7 +290,38 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
         clamp_row(C.rowptr, C.nnz, row, b, e);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         double rs = 0.0;
-        for (int64_t p = b; p < e; ++p) {
+        int64_t p = b;
+        // kM2Unroll entries at a time: their indices, then their S rows, are
+        // loaded together (the loads of one entry no longer wait on the
+        // previous one); the sums still take the entries in order
+        for (; p + kM2Unroll <= e; p += kM2Unroll) {
+            int32_t cc[kM2Unroll];
+            double vv[kM2Unroll], sv[kM2Unroll][4];
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                cc[x] = C.colidx[p + x];
+                vv[x] = C.vals ? static_cast<double>(C.vals[p + x]) : 1.0;
+            }
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                const bool ok = cc[x] >= 0 && cc[x] < C.n_cols;
+                const double* srow = S + (size_t)(ok ? cc[x] : 0) * m;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = lane + 64 * u;
+                    sv[x][u] = (ok && col < m) ? srow[col] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                if (cc[x] < 0 || cc[x] >= C.n_cols) continue;
+                rs += vv[x];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (lane + 64 * u < m) acc[u] += vv[x] * sv[x][u];
+            }
+        }
+        for (; p < e; ++p) {
             const int32_t c = C.colidx[p];
             if (c < 0 || c >= C.n_cols) continue;
             const double v = C.vals ? static_cast<double>(C.vals[p]) : 1.0;
@@ -337,7 +369,39 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const 
         clamp_row(CT.rowptr, CT.nnz, row, b, e);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         double su = 0.0, sm = 0.0;
-        for (int64_t p = b; p < e; ++p) {
+        int64_t p = b;
+        for (; p + kM2Unroll <= e; p += kM2Unroll) {   // as in the first pass
+            int32_t xx[kM2Unroll];
+            double vv[kM2Unroll], tv[kM2Unroll][4], ww2[kM2Unroll], ww1[kM2Unroll];
+#pragma unroll
+            for (int y = 0; y < kM2Unroll; ++y) {
+                xx[y] = CT.colidx[p + y];
+                vv[y] = CT.vals ? static_cast<double>(CT.vals[p + y]) : 1.0;
+            }
+#pragma unroll
+            for (int y = 0; y < kM2Unroll; ++y) {
+                const bool ok = xx[y] >= 0 && xx[y] < CT.n_cols;
+                const int x = ok ? xx[y] : 0;
+                ww2[y] = w2[x];
+                ww1[y] = w1[x];
+                const double* trow = T1 + (size_t)x * m;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = lane + 64 * q;
+                    tv[y][q] = (ok && col < m) ? trow[col] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int y = 0; y < kM2Unroll; ++y) {
+                if (xx[y] < 0 || xx[y] >= CT.n_cols) continue;
+                su += vv[y] * ww2[y];
+                sm += vv[y] * ww1[y];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (lane + 64 * q < m) acc[q] += vv[y] * tv[y][q];
+            }
+        }
+        for (; p < e; ++p) {
             const int32_t x = CT.colidx[p];
             if (x < 0 || x >= CT.n_cols) continue;
             const double v = CT.vals ? static_cast<double>(CT.vals[p]) : 1.0;
