@@ -177,6 +177,9 @@ struct SgdSmem {
     alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * MB * SY : 1];
     alignas(16) Op yct[kStageCT ? KP * SB : 1];
     alignas(16) int32_t idx[MB];
+    // NSTAGE == 0: landing area of the L2 prefetch of the next step's rows
+    // (written by direct-to-LDS loads, never read)
+    alignas(16) uint32_t pf[NSTAGE == 0 ? kWaves * 64 : 1];
     alignas(16) float ybar[3 * KP];
     alignas(16) float m[2 * KP];
     alignas(16) float s[WR * KP];
@@ -759,8 +762,31 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     }
             }
         }
+        if constexpr (NSTAGE == 0) {
+            // the rows of step t+1 (indices loaded in phase 3) start their trip
+            // into L2 now: one 4-byte direct-to-LDS load per 128-byte line of
+            // each row, whose data lands in a scratch area nobody reads; the
+            // products of the next step then read them from L2, not HBM
+            const int tn = t + 1;
+            const bool tr_train = !SCORE || tn < g.end_step;
+            const int tpass = tr_train ? tn / g.spp : 0;
+            const int trow0 = (tr_train ? tn - tpass * g.spp : tn - g.end_step) * B;
+            if (tn < t_end && tid < min(B, n - trow0)) {
+                const int r = nperm ? nrow : trow0 + tid;
+                if (r >= 0 && r < n) {
+                    constexpr int kLineElems = 128 / static_cast<int>(sizeof(Y));
+                    const int nv = (Yv[1] == Yv[0] && Yv[2] == Yv[0]) ? 1 : 3;
+                    for (int v = 0; v < nv; ++v)
+                        for (int c = 0; c < k; c += kLineElems)
+                            __builtin_amdgcn_global_load_lds(
+                                (__attribute__((address_space(1))) void*)(Yv[v] + (size_t)r * ldy + c),
+                                (__attribute__((address_space(3))) void*)(&sm.pf[w * 64]), 4, 0, 0);
+                }
+            }
+        }
         __syncthreads();
     }
+    if constexpr (NSTAGE == 0) __builtin_amdgcn_s_waitcnt(0);   // the prefetches land before the wave ends
 
     if constexpr (SCORE) {
         if (g.score != nullptr) {
