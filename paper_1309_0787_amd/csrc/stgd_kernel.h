@@ -216,6 +216,9 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     constexpr int NCH = (MB * cpr + kThreads - 1) / kThreads;   // chunks per thread when staging
     constexpr int UNR = (M::KI >= 32) ? 4 : 2;     // unroll of the k x k and D contraction loops
     constexpr int UNR_P = 2;                       // and of the batch products (more spills registers)
+    // FP32 without staging: the D product reads its rows from L2 inside the
+    // loop, so more of its iterations are kept in flight
+    constexpr int UNR_D = (NSTAGE == 0 && M::EPL == 1) ? 4 : UNR;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -648,7 +651,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) dacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll UNR
+#pragma unroll UNR_D
             for (int k0 = 0; k0 < MB; k0 += M::KI) {
                 typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
