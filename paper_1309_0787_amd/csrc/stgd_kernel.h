@@ -163,6 +163,19 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int MB = kMaxBatch;           // batch rows padded to 128 in every product
 constexpr int NTM = MB / 16;            // batch tiles
 
+// Four consecutive FP32 row entries a0..a0+3 (0 past k or without a row);
+// a0 is a multiple of 4 and rows are 16-byte aligned (ldy % 4 == 0)
+__device__ __forceinline__ f32x4 yrow4(const float* row, int a0, int k) {
+    if (row == nullptr || a0 >= k) return f32x4{0.f, 0.f, 0.f, 0.f};
+    if (a0 + 4 <= k) return *reinterpret_cast<const f32x4*>(row + a0);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (a0 + e < k) v[e] = row[a0 + e];
+    return v;
+}
+__device__ __forceinline__ f32x4 yrow4(const __bf16*, int, int) { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
 template <class M, int KP, int NSTAGE, int WR = 4>
 struct SgdSmem {
     using Op = typename M::Op;
@@ -213,6 +226,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     constexpr int kTR = NTM / WR;                  // batch tile rows per wave
     constexpr int SP = SM::SP, SB = SM::SB, SY = SM::SY;
     constexpr int cpr = KP / M::CH;                // 16-byte chunks per batch row
+    constexpr int KQ = KP / 4;                     // FP32: k range of one lane group
     constexpr int NCH = (MB * cpr + kThreads - 1) / kThreads;   // chunks per thread when staging
     constexpr int UNR = (M::KI >= 32) ? 4 : 2;     // unroll of the k x k and D contraction loops
     constexpr int UNR_P = 2;                       // and of the batch products (more spills registers)
@@ -430,6 +444,35 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (M::EPL == 1) {
+                // FP32 (one k per lane and instruction): lane group q takes the
+                // k range [q KQ, (q + 1) KQ), so four consecutive k of a row are
+                // one 16-byte LDS read (the order of the k sum is permuted)
+#pragma unroll 1
+                for (int s0 = 0; s0 < KQ; s0 += 4) {
+                    f32x4 fa4[TRK], fb4[TC];
+#pragma unroll
+                    for (int ti = 0; ti < TRK; ++ti) {
+                        const int mt = wr + WR * ti;
+                        fa4[ti] = (mt < NTK) ? M::load4(&sm.phi[(mt * 16 + l16) * SP + q * KQ + s0])
+                                             : f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj) {
+                        const int nt = wc + WC * tj;
+                        fb4[tj] = (nt < NTK) ? M::load4(&sm.phi[(nt * 16 + l16) * SP + q * KQ + s0])
+                                             : f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int ti = 0; ti < TRK; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj < TC; ++tj)
+                                if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                                    acc[ti][tj] = M::mma(fa4[ti][e], fb4[tj][e], acc[ti][tj]);
+                }
+            } else {
 #pragma unroll UNR
             for (int k0 = 0; k0 < KP; k0 += M::KI) {
                 typename M::Frag fa[TRK], fb[TC];
@@ -449,6 +492,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     for (int tj = 0; tj < TC; ++tj)
                         if (wr + WR * ti < NTK && wc + WC * tj < NTK)
                             acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
+            }
             }
             if (SCORE && t == g.end_step) {   // first scoring step: sum of G^3 over live entries
 #pragma unroll
@@ -490,6 +534,35 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) oacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (M::EPL == 1) {
+            // FP32: permuted k as in G; G*G rows give 16-byte reads, the Phi
+            // operand (a-major view of live components) stays one read per k
+#pragma unroll 1
+            for (int s0 = 0; s0 < KQ; s0 += 4) {
+                const int kk = q * KQ + s0;
+                f32x4 fb4[TC];
+#pragma unroll
+                for (int tj = 0; tj < TC; ++tj) {
+                    const int nt = wc + WC * tj;
+                    fb4[tj] = (nt < NTK) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + kk]) : f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float fa1[TRK];
+#pragma unroll
+                    for (int ti = 0; ti < TRK; ++ti) {
+                        const int mt = wr + WR * ti;
+                        fa1[ti] = (mt < NTK && kk + e < k) ? sm.phi[(kk + e) * SP + mt * 16 + l16] : 0.0f;
+                    }
+#pragma unroll
+                    for (int ti = 0; ti < TRK; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < TC; ++tj)
+                            if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                                oacc[ti][tj] = M::mma(fa1[ti], fb4[tj][e], oacc[ti][tj]);
+                }
+            }
+        } else {
 #pragma unroll UNR
         for (int k0 = 0; k0 < KP; k0 += M::KI) {
             typename M::Frag fa[TRK], fb[TC];
@@ -515,6 +588,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 for (int tj = 0; tj < TC; ++tj)
                     if (wr + WR * ti < NTK && wc + WC * tj < NTK)
                         oacc[ti][tj] = M::mma(fa[ti], fb[tj], oacc[ti][tj]);
+        }
         }
         // Phi -= beta kappa O into the register master copy now (compensated),
         // so O is not live through the batch products; the LDS operand copies
@@ -583,6 +657,37 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     pa[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                     pb[tj] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
+                if constexpr (M::EPL == 1) {
+                    // FP32: lane group q takes the k range [q KQ, (q + 1) KQ), so
+                    // four consecutive k of a row are one 16-byte read (as in G)
+#pragma unroll 1
+                    for (int s0 = 0; s0 < KQ; s0 += 4) {
+                        const int kk = q * KQ + s0;
+                        f32x4 fa4, fb4 = {0.f, 0.f, 0.f, 0.f};
+                        if constexpr (NSTAGE == 0) {
+                            fa4 = yrow4(rowA, kk, k);
+                            fb4 = yrow4(rowB, kk, k);
+                        } else {
+                            fa4 = M::load4(sA + kk);
+                            if constexpr (NSTAGE == 3) fb4 = M::load4(sB + kk);
+                        }
+                        f32x4 fp4[TC];
+#pragma unroll
+                        for (int tj = 0; tj < TC; ++tj) {
+                            const int nt = wc + WC * tj;
+                            fp4[tj] = (nt < NTK) ? M::load4(&sm.phi[(nt * 16 + l16) * SP + kk])
+                                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+                        }
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+#pragma unroll
+                            for (int tj = 0; tj < TC; ++tj) {
+                                if (wc + WC * tj >= NTK) continue;
+                                pa[tj] = M::mma(fa4[e], fp4[tj][e], pa[tj]);
+                                if constexpr (NSTAGE != 1) pb[tj] = M::mma(fb4[e], fp4[tj][e], pb[tj]);
+                            }
+                    }
+                } else {
 #pragma unroll UNR_P
                 for (int k0 = 0; k0 < KP; k0 += M::KI) {
                     typename M::Frag fa, fbv;
@@ -602,6 +707,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                             if constexpr (NSTAGE != 1) pb[tj] = M::mma(fbv, fphi, pb[tj]);
                         }
                     }
+                }
                 }
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
@@ -651,6 +757,46 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) dacc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+if constexpr (M::EPL == 1 && NSTAGE > 0) {
+                // FP32 with staged rows: lane group q takes the batch rows
+                // [q MB/4, (q + 1) MB/4), so Q's rows give 16-byte reads; the YC
+                // operand stays one read per row (rows read from L2 instead keep
+                // the loop below, whose iterations overlap their latency)
+                constexpr int KQB = MB / 4;
+#pragma unroll 1
+                for (int s0 = 0; s0 < KQB; s0 += 4) {
+                    const int tt = q * KQB + s0;
+                    f32x4 fb4[TC];
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj) {
+                        const int nt = wc + WC * tj;
+                        fb4[tj] = (nt < NTK) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + tt]) : f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int tr = tt + e;
+                        float fa1[TRK];
+#pragma unroll
+                        for (int ti = 0; ti < TRK; ++ti) {
+                            const int mt = wr + WR * ti;
+                            const int a = mt * 16 + l16;
+                            if (mt >= NTK) {
+                                fa1[ti] = 0.0f;
+                            } else if constexpr (NSTAGE > 0) {
+                                fa1[ti] = sm.ybatch[(vc * MB + tr) * SY + a];
+                            } else {
+                                fa1[ti] = (a < k && tr < nb) ? Yv[2][(size_t)sm.idx[tr] * ldy + a] : 0.0f;
+                            }
+                        }
+#pragma unroll
+                        for (int ti = 0; ti < TRK; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj < TC; ++tj)
+                                if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                                    dacc[ti][tj] = M::mma(fa1[ti], fb4[tj][e], dacc[ti][tj]);
+                    }
+                }
+            } else {
 #pragma unroll UNR_D
             for (int k0 = 0; k0 < MB; k0 += M::KI) {
                 typename M::Frag fa[TRK], fb[TC];
@@ -687,6 +833,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     for (int tj = 0; tj < TC; ++tj)
                         if (wr + WR * ti < NTK && wc + WC * tj < NTK)
                             dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
+            }
             }
             const float invB = 1.0f / static_cast<float>(nb);
 #pragma unroll
