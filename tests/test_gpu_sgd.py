@@ -131,6 +131,26 @@ def test_run_three_views_ragged_batches():
     assert rel(phi_cols(P), ref) < 1e-5
 
 
+@pytest.mark.parametrize("k,three", [(100, True), (128, False), (112, True)])
+def test_run_fp32_unstaged_rows_multi_pass(k, three):
+    """k >= 112 (padded): FP32 rows are not staged in LDS; the products read
+    them from global memory after an L2 prefetch one step ahead.  Several
+    passes with a ragged last batch, against the oracle run."""
+    n, passes = 437, 3
+    YA, YB, YC, ybar, Phi0 = _inputs(n, k, seed=k + 3, three=three)
+    YA, YB, YC, ybar, Phi0 = (f32_round(x) for x in (YA, YB, YC, ybar, Phi0 * 0.8))
+    if not three:
+        YB = YC = YA
+    perms = synth.permutations(n, passes, seed=k)
+    ref = oracle.sgd_run(YA, YB, YC, ybar, Phi0, perms, 100, 0.01, 20.0, 0.4)
+    A, B, C = _dev_views(YA, YB, YC, k, otm.F32)
+    P = phi_rows(Phi0)
+    p = otm.SgdParams(k=k, batch=100, passes=passes, alpha0=0.4, beta0=0.01, beta_tau=20.0)
+    otm.sgd_run(p, n, A, B, C, to_dev(ybar), to_dev(perms, torch.int32), P)
+    torch.cuda.synchronize()
+    assert rel(phi_cols(P), ref) < 1e-5
+
+
 def test_run_split_restarts_snapshots_bit_identical():
     n, k, passes = 300, 16, 3
     YA, YB, YC, ybar, _ = _inputs(n, k, seed=13)
