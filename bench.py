@@ -20,11 +20,6 @@ import os
 import sys
 import time
 
-# The batched leg runs one persistent kernel per kernel variant (ten here) side
-# by side; HIP gives a process GPU_MAX_HW_QUEUES hardware queues (4 by
-# default), so the benchmark asks for 16 before the runtime starts.
-os.environ["GPU_MAX_HW_QUEUES"] = "16"
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -427,4 +422,8 @@ def main():
 
 
 if __name__ == "__main__":
+    # The batched leg runs one persistent kernel per kernel variant (ten here)
+    # side by side; HIP gives a process GPU_MAX_HW_QUEUES hardware queues (4 by
+    # default), so the benchmark asks for 16 before the runtime starts.
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
     main()
