@@ -44,10 +44,15 @@ def sgd_flops(n: int, batch: int, k: int, passes: int) -> float:
 
 
 def kernel_hash() -> str:
-    """Hash of the STGD kernel's sources (the counters are valid for these only)."""
+    """Hash of the STGD kernel's sources without comments and blank lines (the
+    counters are valid for this code only)."""
+    import re
     h = hashlib.sha256()
     for f in ("stgd.hip", "stgd_kernel.h"):
-        h.update(open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(line.rstrip() for line in src.splitlines() if line.strip()).encode())
     return h.hexdigest()[:16]
 
 

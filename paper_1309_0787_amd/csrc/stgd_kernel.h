@@ -23,11 +23,17 @@
 // to the operand layout, the mini-batch of whitened rows, and small vectors.
 //
 // Batch staging (NSTAGE = 1 for one shared view, 3 for three views): the rows
-// of step t+1 are fetched into registers while step t computes (indices during
-// the Phi^T Phi and Phi (G*G) products, data during the rest) and written to
-// LDS row-major at the start of step t+1, so the products never wait on
-// global memory.  NSTAGE = 0 (shapes whose batch does not fit in LDS) reads
-// the rows from global memory inside the products.
+// of step t+1 are fetched into registers while step t computes (their indices
+// were fetched during step t-1) and written to LDS row-major at the start of
+// step t+1, so the products never wait on global memory; no load is waited on
+// right after it is issued (checks and masks happen where the values are
+// used).  NSTAGE = 0 (shapes whose batch does not fit in LDS) reads the rows
+// from global memory inside the products, after pulling the next step's rows
+// into L2 at the end of each step.
+//
+// FP32 operands (one k per lane and MFMA): lane group q takes a contiguous k
+// range, so four consecutive k are one 16-byte LDS read; the k sum is the same
+// set of products in another order.
 //
 // Four workgroup barriers per step: after G*G, after O (the buffer then
 // takes Q), after Q, after the update.  The batch is padded to 128 rows in
