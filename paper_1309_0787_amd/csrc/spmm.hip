@@ -64,13 +64,30 @@ __device__ __forceinline__ void clamp_row(const int32_t* rowptr, int64_t nnz, in
 }
 
 // Y = diag(r) C W ; per-block column sums of the FP32 rows into part[0..k)[blockIdx]
-template <int VPL, int LPR, class TW, class TY>
-__global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int normalize, const TW* __restrict__ W,
-                                                              int k, int ldw, TY* __restrict__ Y, int ldy,
-                                                              float* __restrict__ part) {
+// LDSW: the whole of W (n_cols rows of ks = k rounded up to VPL entries) is
+// first copied into LDS by the workgroup, and the rows are gathered from there
+// (for a W of at most about 128 KB; NT threads, one workgroup per CU).
+template <int VPL, int LPR, class TW, class TY, int NT = kSpmmThreads, bool LDSW = false>
+__global__ __launch_bounds__(NT) void whiten_kernel(otm_csr C, int normalize, const TW* __restrict__ W,
+                                                   int k, int ldw, TY* __restrict__ Y, int ldy,
+                                                   float* __restrict__ part) {
     constexpr int lpr = LPR;
-    constexpr int rows_per_block = kSpmmThreads / LPR;
+    constexpr int rows_per_block = NT / LPR;
     __shared__ float s_colsum[rows_per_block * LPR * VPL];
+    extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+    TW* s_w = reinterpret_cast<TW*>(s_dyn);
+    const int ks = (k + VPL - 1) / VPL * VPL;    // LDS row stride of W
+    if constexpr (LDSW) {
+        using V = typename WVec<VPL, TW>::T;
+        const int vpr = ks / VPL;
+        const int nvec = C.n_cols * vpr;
+        for (int q = threadIdx.x; q < nvec; q += NT) {
+            const int r = q / vpr, cv = q - r * vpr;
+            *reinterpret_cast<V*>(s_w + r * ks + cv * VPL) =
+                *reinterpret_cast<const V*>(W + (size_t)r * ldw + cv * VPL);
+        }
+        __syncthreads();
+    }
     const int tid = threadIdx.x;
     const int g_lane = tid % LPR;          // lane within the row group
     const int slot = tid / LPR;
@@ -113,8 +130,10 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        if (active && c4[u] >= 0) load_w<VPL>(W + (size_t)c4[u] * ldw + col0, w4[u]);
-                        else {
+                        if (active && c4[u] >= 0) {
+                            if constexpr (LDSW) load_w<VPL>(s_w + c4[u] * ks + col0, w4[u]);
+                            else load_w<VPL>(W + (size_t)c4[u] * ldw + col0, w4[u]);
+                        } else {
 #pragma unroll
                             for (int v = 0; v < VPL; ++v) w4[u][v] = 0.f;
                         }
@@ -130,8 +149,10 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
                     const int c = __shfl(my_col, jj, lpr);
                     const float val = __shfl(my_val, jj, lpr);
                     float w1[VPL];
-                    if (active && c >= 0) load_w<VPL>(W + (size_t)c * ldw + col0, w1);
-                    else {
+                    if (active && c >= 0) {
+                        if constexpr (LDSW) load_w<VPL>(s_w + c * ks + col0, w1);
+                        else load_w<VPL>(W + (size_t)c * ldw + col0, w1);
+                    } else {
 #pragma unroll
                         for (int v = 0; v < VPL; ++v) w1[v] = 0.f;
                     }
@@ -173,7 +194,7 @@ __global__ __launch_bounds__(kSpmmThreads) void whiten_kernel(otm_csr C, int nor
 #pragma unroll
     for (int v = 0; v < VPL; ++v) s_colsum[slot * width + col0 + v] = colacc[v];
     __syncthreads();
-    for (int c = tid; c < k; c += kSpmmThreads) {
+    for (int c = tid; c < k; c += NT) {
         float s = 0.f;
         for (int sl = 0; sl < rows_per_block; ++sl) s += s_colsum[sl * width + c];
         part[(size_t)c * gridDim.x + blockIdx.x] = s;     // column-major: the finalize reads it coalesced
@@ -231,6 +252,31 @@ int dispatch_lpr(int lpr, const otm_csr& C, int normalize, const void* W, int k,
     }
 }
 
+constexpr int kLdsWThreads = 1024;
+constexpr int kLdsWMinRow = 64;     // mean stored entries per row below which W stays in global memory
+
+template <int VPL, int LPR, class TW, class TY>
+int launch_whiten_lds(const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy, float* part,
+                      int nblocks, hipStream_t st) {
+    const int ks = (k + VPL - 1) / VPL * VPL;
+    const size_t shm = sizeof(TW) * (size_t)C.n_cols * ks;
+    hipLaunchKernelGGL((whiten_kernel<VPL, LPR, TW, TY, kLdsWThreads, true>), dim3(nblocks), dim3(kLdsWThreads), shm,
+                       st, C, normalize, static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part);
+    return check_launch("whiten_kernel (W in LDS)");
+}
+
+template <class TW, class TY>
+int dispatch_whiten_lds(int lpr, const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy,
+                        float* part, int nblocks, hipStream_t st) {
+    constexpr int V = 16 / static_cast<int>(sizeof(TW));
+    switch (lpr) {
+        case 8: return launch_whiten_lds<V, 8, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 16: return launch_whiten_lds<V, 16, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        case 32: return launch_whiten_lds<V, 32, TW, TY>(C, normalize, W, k, ldw, Y, ldy, part, nblocks, st);
+        default: return fail(OTM_EINVAL, "bad lanes per row");
+    }
+}
+
 template <class TW, class TY>
 int dispatch_whiten(int vpl, const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy,
                     float* part, int nblocks, int lpr, hipStream_t st) {
@@ -246,7 +292,21 @@ int dispatch_whiten(int vpl, const otm_csr& C, int normalize, const void* W, int
 
 struct WhitenPlan {
     int vpl, lpr, nblocks;
+    bool lds;          // W staged in LDS (whiten_kernel<..., LDSW = true>)
 };
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            return 256;
+    }
+    return cus;
+}
 
 // Widest vector (at most 16 bytes) that the row stride, the base alignment and
 // the row length allow: ldw % vpl == 0, W aligned to the vector, and the last
@@ -268,7 +328,35 @@ WhitenPlan plan_whiten(int32_t n_rows, int k, int ldw, int w_dtype, uintptr_t w_
     if (blocks > kSpmmMaxBlocks) blocks = kSpmmMaxBlocks;
     if (blocks < 1) blocks = 1;
     p.nblocks = static_cast<int>(blocks);
+    p.lds = false;
     return p;
+}
+
+// W in LDS pays when it fits beside the column-sum buffer, every column is
+// gathered many times per workgroup (each of one or two workgroups per CU
+// copies all of W once: at least 512 stored entries per column of W), and the
+// rows are long (at least 64 entries on average): with short rows the row
+// pointers, values and Y stores dominate and the L2 gathers cost the same.
+void plan_whiten_lds(WhitenPlan& p, const otm_csr& C, int k, int w_dtype) {
+    const int esize = (w_dtype == OTM_BF16) ? 2 : 4;
+    if (p.vpl != 16 / esize || (p.lpr != 8 && p.lpr != 16 && p.lpr != 32)) return;
+    const size_t ks = (size_t)(k + p.vpl - 1) / p.vpl * p.vpl;
+    const size_t w_bytes = ks * esize * (size_t)C.n_cols;
+    const size_t colsum_bytes = sizeof(float) * kLdsWThreads * p.vpl;
+    const size_t need = w_bytes + colsum_bytes + 1024;
+    if (C.n_cols < 1 || need > 160 * 1024) return;
+    if (C.nnz < (int64_t)512 * C.n_cols) return;            // each W row gathered often enough to pay its copy
+    if (C.nnz < (int64_t)kLdsWMinRow * C.n_rows) return;    // short rows: no gain over the L2 gathers
+    // two workgroups per CU (8 waves per SIMD) where W fits twice and the
+    // kernel's registers allow it (the FP32 variant stays under 64 VGPRs)
+    const int per_cu = (esize == 4 && 2 * need <= 160 * 1024) ? 2 : 1;
+    const int rpb = kLdsWThreads / p.lpr;
+    int64_t blocks = (C.n_rows + rpb - 1) / rpb;
+    const int64_t cap = (int64_t)device_cus() * per_cu;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    p.nblocks = static_cast<int>(blocks);
+    p.lds = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +573,7 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
     OTM_REQUIRE(y_dtype == OTM_F32 || y_dtype == OTM_BF16, OTM_EDTYPE, "Y must be F32 or BF16");
     OTM_REQUIRE(y_dtype != OTM_BF16 || ldy % 8 == 0, OTM_ESHAPE, "BF16 Y needs ldy % 8 == 0");
     OTM_REQUIRE(y_dtype != OTM_F32 || ldy % 4 == 0, OTM_ESHAPE, "F32 Y needs ldy % 4 == 0");
-    const WhitenPlan p = plan_whiten(C->n_rows, k, ldw, w_dtype, reinterpret_cast<uintptr_t>(W));
+    WhitenPlan p = plan_whiten(C->n_rows, k, ldw, w_dtype, reinterpret_cast<uintptr_t>(W));
     OTM_REQUIRE(p.lpr <= 64, OTM_ECAPACITY, "k too large for the whitening kernel (k <= 64 * vector width)");
     OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whiten_workspace(C->n_rows, k), OTM_EWORKSPACE,
                 "whiten workspace too small");
@@ -498,7 +586,17 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
     }
     hipStream_t s = as_stream(stream);
     float* part = static_cast<float*>(ws);
-    if (w_dtype == OTM_F32) {
+    plan_whiten_lds(p, *C, k, w_dtype);
+    if (p.lds) {
+        if (w_dtype == OTM_F32)
+            st = (y_dtype == OTM_F32)
+                     ? dispatch_whiten_lds<float, float>(p.lpr, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, s)
+                     : dispatch_whiten_lds<float, __bf16>(p.lpr, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, s);
+        else
+            st = (y_dtype == OTM_F32)
+                     ? dispatch_whiten_lds<__bf16, float>(p.lpr, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, s)
+                     : dispatch_whiten_lds<__bf16, __bf16>(p.lpr, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, s);
+    } else if (w_dtype == OTM_F32) {
         st = (y_dtype == OTM_F32)
                  ? dispatch_whiten<float, float>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s)
                  : dispatch_whiten<float, __bf16>(p.vpl, *C, normalize, W, k, ldw, Y, ldy, part, p.nblocks, p.lpr, s);

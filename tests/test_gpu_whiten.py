@@ -97,6 +97,47 @@ def test_whiten_document_views_padded_stride():
         np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
 
 
+@pytest.mark.parametrize("k", [50, 100])
+@pytest.mark.parametrize("w_dt,y_dt", [(otm.F32, otm.F32), (otm.BF16, otm.BF16), (otm.BF16, otm.F32)])
+def test_whiten_w_in_lds(k, w_dt, y_dt):
+    """A small W (300 rows) gathered by many stored entries (over 512 per
+    column, rows of 80 entries on average) is copied into LDS once per
+    workgroup; the rows equal the oracle's and, bit for bit, those of the
+    kernel that gathers W from global memory (forced by a row stride that
+    allows only narrow vectors).  Row lengths are ragged, some rows empty, and
+    the row count is not a multiple of the rows a workgroup takes."""
+    rng = np.random.default_rng(k)
+    d, n = 300, 6001
+    lens = rng.integers(48, 113, n)
+    lens[rng.choice(n, 20, replace=False)] = 0
+    cols = [np.sort(rng.choice(d, int(m), replace=False)) for m in lens]
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    colidx = np.concatenate(cols).astype(np.int32)
+    vals = rng.integers(1, 5, colidx.size).astype(np.float32)
+    assert colidx.size >= 512 * d and colidx.size >= 64 * n
+    C = synth.CSR(n, d, rowptr, colidx, vals)
+    W = synth.projection(d, k, seed=12)
+    Wr = bf16_round(W) if w_dt == otm.BF16 else f32_round(W)
+    tdt = torch.bfloat16 if w_dt == otm.BF16 else torch.float32
+    Cd = csr_dev(C)
+    fast = torch.zeros((d, otm.default_ldw(k, w_dt)), dtype=tdt, device=dev())
+    fast[:, :k] = to_dev(Wr, tdt)
+    slow = torch.zeros((d, k + 1 if k % 2 else k + 2), dtype=tdt, device=dev())   # narrow vectors, 64 lanes
+    slow[:, :k] = to_dev(Wr, tdt)
+    for norm in (False, True):
+        Y, ybar = otm.whiten(Cd, norm, fast[:, :k], y_dtype=y_dt)
+        Y2, ybar2 = otm.whiten(Cd, norm, slow[:, :k], y_dtype=y_dt)
+        torch.cuda.synchronize()
+        Yref, ybref = oracle.whiten(C, Wr, normalize=False)
+        if norm:     # an empty row has no token count: the kernel writes zeros there
+            Yref = np.where(lens[:, None] > 0, Yref / np.asarray(C.to_scipy().sum(1)).clip(1e-30), 0.0)
+            ybref = Yref.mean(0)
+        _check_rows(host(Y), Yref, k, 2e-6 if y_dt == otm.F32 else 2.0 ** -8)
+        assert torch.equal(Y, Y2)
+        np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
+        np.testing.assert_allclose(host(ybar), host(ybar2), rtol=0, atol=1e-6 * np.abs(ybref).max())
+
+
 def test_whiten_empty_rows_and_empty_matrix():
     # rows 0, 3 and the last are empty
     rowptr = np.array([0, 0, 2, 3, 3, 5, 5], dtype=np.int32)
