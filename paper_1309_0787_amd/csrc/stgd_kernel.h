@@ -69,7 +69,6 @@ struct MmaF32 {
     static constexpr int EPL = 1;
     static constexpr int SPAD = 4;            // LDS row padding (elements)
     static constexpr int CH = 4;              // elements per chunk
-    static constexpr bool kPhiT = false;
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -104,11 +103,27 @@ struct MmaBF16 {
     // 12 banks measured about 4% slower per step at k = 128)
     static constexpr int SPAD = 16;
     static constexpr int CH = 8;
-    static constexpr bool kPhiT = true;
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
     __device__ static Frag lds(const Op* p) { return *reinterpret_cast<const bf16x8*>(p); }
+    // Fragment of a matrix stored the other way round: lane l receives
+    // X[8 (l/16) + e][l % 16], e < 8, where X[r][c] = x[r * stride + c] in
+    // LDS.  Two transposing 8-byte reads (rows 0-3 and 4-7 of the lane's
+    // group): lane s addresses columns 4 (s % 4) .. + 3 of row
+    // 8 (s/16) + (s % 16)/4, and element i of lane l comes from element l % 4
+    // of lane 16 (l/16) + (l % 16)/4 + 4 i.  x and stride keep every address
+    // 8-byte aligned.
+    __device__ static Frag lds_t(const Op* x, int stride, int lane) {
+        typedef short s16x4 __attribute__((ext_vector_type(4)));
+        typedef short s16x8 __attribute__((ext_vector_type(8)));
+        typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+        const Op* p = x + (8 * (lane >> 4) + ((lane >> 2) & 3)) * stride + 4 * (lane & 3);
+        const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p));
+        const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * stride));
+        const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_bit_cast(Frag, v);
+    }
     __device__ static Op to_op(float x) { return f32_to_bf16(x); }
     __device__ static float op_to_f(Op x) { return bf16_to_f32(x); }
     __device__ static Frag zero_frag() {
@@ -189,9 +204,9 @@ struct SgdSmem {
     static constexpr int SP = KP + M::SPAD;        // Phi rows
     static constexpr int SB = MB + M::SPAD;        // exchange buffer rows (t or j)
     static constexpr int SY = KP + M::SPAD;        // staged batch rows
-    static constexpr bool kStageCT = (NSTAGE == 0) && M::kPhiT;   // BF16 fallback: YC batch a-major
+    static constexpr bool kStageCT = (NSTAGE == 0) && M::EPL == 8;   // BF16 fallback: YC batch a-major
     alignas(16) Op phi[KP * SP];
-    alignas(16) Op phiT[M::kPhiT ? KP * SP : 1];
+    alignas(16) Op yfold[2 * SP];                  // ybarA, ybarB rows of the Phi^T Phi fold
     alignas(16) Op buf[KP * SB];
     alignas(16) Y ybatch[NSTAGE > 0 ? NSTAGE * MB * SY : 1];
     alignas(16) Op yct[kStageCT ? KP * SB : 1];
@@ -259,10 +274,12 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const Y* Yv[3] = {static_cast<const Y*>(g.YA), static_cast<const Y*>(g.YB), static_cast<const Y*>(g.YC)};
     bool bad = false;
     const float cmask = g.compensated ? 1.0f : 0.0f;
+    constexpr bool kFoldO = !(M::EPL == 1 && KP == 112);
     // mA = Phi^T ybarA and mB = Phi^T ybarB ride along in Phi^T Phi when two
-    // padding rows are free: the phi_i-major operand holds ybarA, ybarB as
-    // "components" k and k+1 (never updated, zero in the a-major copy), so
-    // G[i][k] = mA[i] and G[i][k+1] = mB[i].
+    // padding rows are free: the second operand of that product takes ybarA,
+    // ybarB (the yfold rows) as "components" k and k+1, so G[i][k] = mA[i] and
+    // G[i][k+1] = mB[i].  Every other product reads the zero rows k, k+1 of
+    // the Phi copy, so G[k][.] and G[k+1][.] are zero as well.
     const bool mfold = (k + 2 <= KP);
 
     // ---- master copy of Phi in registers: tile (mt, nt) holds a = row, i = column
@@ -281,16 +298,9 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     if (a < k && i < k) {
                         v[r] = Phi0[(size_t)i * k + a];
                         if (Comp && g.compensated) cv[r] = Comp[(size_t)i * k + a];
-                    } else if (mfold && a < k && (i == k || i == k + 1)) {
-                        v[r] = g.ybar[(i - k) * k + a];
                     }
                 }
                 M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
-                if constexpr (M::kPhiT) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(i < k ? v[r] : 0.0f);
-                }
             }
             phi[ti][tj] = v;
             comp[ti][tj] = cv;
@@ -298,6 +308,17 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     for (int e = tid; e < 3 * KP; e += kThreads) {
         const int v = e / KP, a = e % KP;
         sm.ybar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
+    }
+    for (int e = tid; e < 2 * SP; e += kThreads) {
+        const int v = e / SP, a = e % SP;
+        sm.yfold[e] = M::to_op((a < k) ? g.ybar[v * k + a] : 0.0f);
+    }
+    // rows of the second operand of Phi^T Phi: component i, or a mean at k, k+1
+    const Op* grow[TC];
+#pragma unroll
+    for (int tj = 0; tj < TC; ++tj) {
+        const int i = (wc + WC * tj < NTK) ? (wc + WC * tj) * 16 + l16 : 0;
+        grow[tj] = (mfold && (i == k || i == k + 1)) ? &sm.yfold[(i - k) * SP] : &sm.phi[i * SP];
     }
     // per-column factor of the update: 1 for a live component, 0 for padding
     float live[TC];
@@ -466,8 +487,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        fb4[tj] = (nt < NTK) ? M::load4(&sm.phi[(nt * 16 + l16) * SP + q * KQ + s0])
-                                             : f32x4{0.f, 0.f, 0.f, 0.f};
+                        fb4[tj] = (nt < NTK) ? M::load4(grow[tj] + q * KQ + s0) : f32x4{0.f, 0.f, 0.f, 0.f};
                     }
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
@@ -490,7 +510,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
+                    fb[tj] = (nt < NTK) ? M::lds(grow[tj] + k0 + q * M::EPL) : M::zero_frag();
                 }
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
@@ -577,8 +597,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 const int mt = wr + WR * ti;
                 const int a = mt * 16 + l16;
                 if (mt < NTK) {
-                    if constexpr (M::kPhiT) fa[ti] = M::lds(&sm.phiT[a * SP + k0 + q * M::EPL]);
-                    else fa[ti] = (k0 + q < k) ? sm.phi[(k0 + q) * SP + a] : 0.0f;   // a-major view, live columns
+                    // Phi[a][i], i = k0 + EPL q + e, from the component-major copy
+                    fa[ti] = M::lds_t(&sm.phi[k0 * SP + mt * 16], SP, lane);
                 } else {
                     fa[ti] = M::zero_frag();
                 }
@@ -596,10 +616,13 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                         oacc[ti][tj] = M::mma(fa[ti], fb[tj], oacc[ti][tj]);
         }
         }
-        // Phi -= beta kappa O into the register master copy now (compensated),
-        // so O is not live through the batch products; the LDS operand copies
-        // keep the old Phi, which every product of this step reads, until the
-        // direction term is added at the end of the step
+        // -beta kappa O goes into the compensation term now (c <- c + beta
+        // kappa O), so O is not live through the batch products; the single
+        // compensated addition at the end of the step then adds the whole
+        // increment beta (D - kappa O) to the master copy.  The LDS operand
+        // copies keep the old Phi, which every product of this step reads.
+        // (FP32 at KP = 112 keeps two compensated additions: there the fold
+        // made the register allocator spill more, and the step was slower.)
         if (!SCORE || train) {
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
@@ -607,16 +630,18 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
-                    f32x4 v = phi[ti][tj], cv = comp[ti][tj];
+                    if constexpr (kFoldO) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float y = -f3 * oacc[ti][tj][r] - cv[r];
-                        const float tt = v[r] + y;
-                        cv[r] = ((tt - v[r]) - y) * cmask;
-                        v[r] = tt;
+                        for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
+                    } else {   // a compensated addition of its own
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float y = -f3 * oacc[ti][tj][r] - comp[ti][tj][r];
+                            const float tt = phi[ti][tj][r] + y;
+                            comp[ti][tj][r] = ((tt - phi[ti][tj][r]) - y) * cmask;
+                            phi[ti][tj][r] = tt;
+                        }
                     }
-                    phi[ti][tj] = v;
-                    comp[ti][tj] = cv;
                 }
             }
         }
@@ -817,9 +842,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                         if constexpr (M::EPL == 1) {
                             fa[ti] = sm.ybatch[(vc * MB + k0 + q) * SY + a];
                         } else {
-#pragma unroll
-                            for (int e = 0; e < M::EPL; ++e)
-                                fa[ti][e] = sm.ybatch[(vc * MB + k0 + q * M::EPL + e) * SY + a];
+                            fa[ti] = M::lds_t(&sm.ybatch[(vc * MB + k0) * SY + mt * 16], SY, lane);
                         }
                     } else if constexpr (SM::kStageCT) {
                         fa[ti] = M::lds(&sm.yct[a * SB + k0 + q * M::EPL]);
@@ -864,8 +887,8 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     score_t += static_cast<double>(nb) / static_cast<double>(n) * static_cast<double>(part * live[tj]);
                     continue;
                 }
-                // delta = beta*live*(dacc/B + ybarC*rv), folded per column (the
-                // -beta*kappa*O part went in after phase 2)
+                // delta = beta*live*(dacc/B + ybarC*rv), folded per column; the
+                // compensation term already holds +beta*kappa*O
                 const float bl = beta * live[tj];
                 const float f1 = bl * invB, f2 = bl * rv;
 #pragma unroll
@@ -876,9 +899,8 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     f32x4 v = phi[ti][tj], cv = comp[ti][tj];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float delta = fmaf(f1, dacc[ti][tj][r], f2 * ybc[r]);
                         // Kahan step; cmask = 0 turns it into the plain update
-                        const float y = delta - cv[r];
+                        const float y = fmaf(f1, dacc[ti][tj][r], f2 * ybc[r]) - cv[r];
                         const float tt = v[r] + y;
                         cv[r] = ((tt - v[r]) - y) * cmask;
                         v[r] = tt;
@@ -886,10 +908,6 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     phi[ti][tj] = v;
                     comp[ti][tj] = cv;
                     M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
-                    if constexpr (M::kPhiT) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) sm.phiT[(mt * 16 + 4 * q + r) * SP + i] = M::to_op(v[r] * live[tj]);
-                    }
                 }
             }
             if (train && (s == g.spp - 1 || t + 1 == g.end_step)) {
