@@ -51,6 +51,7 @@ int jacobi(double* A, double* V, int n, double* evals, int* order, void* ws, hip
 
 // ------------------------------------------------------------- numerics
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));

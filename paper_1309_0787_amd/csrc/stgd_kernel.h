@@ -88,6 +88,16 @@ struct MmaF32 {
         return v;
     }
     __device__ static Chunk zero_chunk() { return Chunk{0.f, 0.f, 0.f, 0.f}; }
+    // bit mask of the first `valid` elements of a chunk, and a chunk ANDed with it
+    __device__ static u32x4 chunk_mask(int valid) {
+        u32x4 m;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) m[d] = (d < valid) ? 0xffffffffu : 0u;
+        return m;
+    }
+    __device__ static Chunk and_chunk(Chunk x, u32x4 m) {
+        return __builtin_bit_cast(Chunk, __builtin_bit_cast(u32x4, x) & m);
+    }
     __device__ static void store4(Op* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
     __device__ static f32x4 load4(const Op* p) { return *reinterpret_cast<const f32x4*>(p); }
 };
@@ -150,6 +160,18 @@ struct MmaBF16 {
         return v;
     }
     __device__ static Chunk zero_chunk() { return zero_frag(); }
+    // bit mask of the first `valid` elements of a chunk (two per dword), and a
+    // chunk ANDed with it
+    __device__ static u32x4 chunk_mask(int valid) {
+        u32x4 m;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            m[d] = ((2 * d < valid) ? 0x0000ffffu : 0u) | ((2 * d + 1 < valid) ? 0xffff0000u : 0u);
+        return m;
+    }
+    __device__ static Chunk and_chunk(Chunk x, u32x4 m) {
+        return __builtin_bit_cast(Chunk, __builtin_bit_cast(u32x4, x) & m);
+    }
     __device__ static void store4(Op* p, f32x4 v) {
         bf16x4 o;
         o[0] = f32_to_bf16(v[0]);
@@ -250,7 +272,10 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     constexpr int KQ = KP / 4;                     // FP32: k range of one lane group
     constexpr int NCH = (MB * cpr + kThreads - 1) / kThreads;   // chunks per thread when staging
     constexpr int UNR = (M::KI >= 32) ? 4 : 2;     // unroll of the k x k and D contraction loops
-    constexpr int UNR_P = 2;                       // and of the batch products (more spills registers)
+    // and of the batch products: fully unrolled for staged BF16 rows (the first
+    // MFMA then starts from zero without clearing registers); FP32 and
+    // unstaged rows spill registers beyond 2
+    constexpr int UNR_P = (M::EPL == 8 && NSTAGE > 0) ? 4 : 2;
     // FP32 without staging: the D product reads its rows from L2 inside the
     // loop, so more of its iterations are kept in flight
     constexpr int UNR_D = (NSTAGE == 0 && M::EPL == 1) ? 4 : UNR;
@@ -335,6 +360,14 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     // (a loaded index is only ever read where the rows are loaded: selecting
     // between it and anything else right after the load would wait for it)
     typename M::Chunk pbuf[NSTAGE > 0 ? NSTAGE : 1][NCH];
+    // when the thread count is a multiple of the chunks per row, all chunks of
+    // a thread start at the same column a0t
+    constexpr bool kA0Const = (kThreads % cpr) == 0;
+    const int a0t = (tid % cpr) * M::CH;
+    const u32x4 a0mask = M::chunk_mask(k - a0t);
+    if constexpr (NSTAGE > 0 && kA0Const) {   // the parts of the staging area that are never written stay zero
+        for (int e = tid; e < NSTAGE * MB * SY; e += kThreads) sm.ybatch[e] = M::to_op(0.0f);
+    }
     // steps t >= end_step (up to t_end) are the scoring pass: rows in natural order
     const int t_end = g.end_step + ((SCORE && g.score != nullptr) ? g.spp : 0);
     auto issue_index = [&](int t) {
@@ -360,29 +393,85 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         }
     };
     auto issue_data = [&]() {
-        if constexpr (NSTAGE > 0) {
+        // The rows of every chunk are chosen first and loaded after: a row
+        // chosen after an earlier chunk's load was issued would make that
+        // choice wait for the load (the wait counter drains in issue order).
+        if constexpr (NSTAGE > 0 && kA0Const) {
+            // every chunk of this thread starts at column a0t: threads past k
+            // load nothing (their LDS columns stay zero), rows past the batch
+            // size are never staged, and a row outside the batch loads row 0
+            // (cleared at commit)
+            int32_t rsel[NCH];
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
-                const int a0 = (c % cpr) * M::CH;
+                const bool live_c = (plive >> j) & 1u;
+                const int32_t r = pperm ? pidx[j] : prow0 + c / cpr;
+                const bool in_range = r >= 0 && r < n;
+                if (live_c && !in_range) bad = true;   // out-of-range permutation entry: reads row 0, reported
+                rsel[j] = (live_c && in_range) ? r : 0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
+                if (c < MB * cpr && c / cpr < B && a0t < k && n > 0) {
+#pragma unroll
+                    for (int v = 0; v < NSTAGE; ++v)
+                        pbuf[v][j] = *reinterpret_cast<const typename M::Chunk*>(Yv[v] + (size_t)rsel[j] * ldy + a0t);
+                }
+            }
+        } else if constexpr (NSTAGE > 0) {
+            int32_t rsel[NCH];
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
                 const bool live_c = (plive >> j) & 1u;
                 int32_t r = pperm ? pidx[j] : prow0 + c / cpr;
                 if (live_c && (r < 0 || r >= n)) {   // out-of-range permutation entry: reads row 0, reported
                     r = 0;
                     bad = true;
                 }
+                rsel[j] = r;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int c = tid + j * kThreads;
+                const int a0 = (c % cpr) * M::CH;
+                const bool live_c = (plive >> j) & 1u;
                 // the columns past k of a row's last chunk are cleared at commit,
                 // so nothing here waits for the load
 #pragma unroll
                 for (int v = 0; v < NSTAGE; ++v)
                     pbuf[v][j] = (live_c && a0 < k) ? *reinterpret_cast<const typename M::Chunk*>(
-                                                          Yv[v] + (size_t)r * ldy + a0)
+                                                          Yv[v] + (size_t)rsel[j] * ldy + a0)
                                                     : M::zero_chunk();
             }
         }
     };
-    auto commit = [&]() {
-        if constexpr (NSTAGE > 0) {
+    auto commit = [&](int nb) {
+        if constexpr (NSTAGE > 0 && kA0Const) {
+            // columns past k cleared with the thread's constant mask; rows past
+            // nb of a short batch cleared as well
+            auto store = [&](bool partial) {
+#pragma unroll
+                for (int j = 0; j < NCH; ++j) {
+                    const int c = tid + j * kThreads;
+                    const int tr = c / cpr;
+                    if (c < MB * cpr && tr < B && a0t < k) {
+#pragma unroll
+                        for (int v = 0; v < NSTAGE; ++v) {
+                            typename M::Chunk x = M::and_chunk(pbuf[v][j], a0mask);
+                            if (partial && tr >= nb) x = M::zero_chunk();
+                            *reinterpret_cast<typename M::Chunk*>(&sm.ybatch[(v * MB + tr) * SY + a0t]) = x;
+                        }
+                    }
+                }
+            };
+            if (nb == B) store(false);   // a scalar branch: full batches skip the row test
+            else store(true);
+        } else if constexpr (NSTAGE > 0) {
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int c = tid + j * kThreads;
@@ -425,7 +514,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         const float beta = g.beta0 / (1.0f + static_cast<float>(t) * g.inv_tau);
 
         // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
-        commit();
+        commit(nb);
         if constexpr (NSTAGE == 0) {
             if (tid < nb) {
                 int32_t r = nperm ? nrow : row0 + tid;
