@@ -284,22 +284,21 @@ __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* _
     }
     __syncthreads();
     const double dmax = s_dmax;
-    // right-looking Cholesky, one column per step
+    // right-looking Cholesky, one column per step.  The diagonal entry keeps
+    // the pivot (every thread takes its square root itself, so no step waits
+    // for one thread) until the loop ends.
     for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            double dj = sL[low_idx(j, j)];
-            if (!(dj > 1e-14 * dmax)) {
-                s_bad = 1;
-                dj = dmax > 0.0 ? dmax : 1.0;
-            }
-            sL[low_idx(j, j)] = sqrt(dj);
+        double* cj = colj;
+        double dj = sL[low_idx(j, j)];
+        if (!(dj > 1e-14 * dmax)) {   // not positive definite to working precision: reported, pivot replaced
+            if (tid == 0) s_bad = 1;
+            dj = dmax > 0.0 ? dmax : 1.0;
         }
-        __syncthreads();
-        const double inv = 1.0 / sL[low_idx(j, j)];
+        const double inv = 1.0 / sqrt(dj);
         for (int i = j + 1 + tid; i < m; i += kCholThreads) {
             const double v = sL[low_idx(i, j)] * inv;
             sL[low_idx(i, j)] = v;
-            colj[i] = v;
+            cj[i] = v;
         }
         __syncthreads();
         // trailing update A[i][l] -= L[i][j] L[l][j], j < l <= i, S threads per row
@@ -309,21 +308,29 @@ __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* _
             const int row = tid / S, sub = tid % S;
             if (row < w) {
                 const int i = j + 1 + row;
-                const double lij = colj[i];
+                const double lij = cj[i];
                 double* Li = sL + low_idx(i, 0);
-                for (int l = j + 1 + sub; l <= i; l += S) Li[l] -= lij * colj[l];
+                for (int l = j + 1 + sub; l <= i; l += S) Li[l] -= lij * cj[l];
             }
         }
         __syncthreads();
     }
+    for (int j = tid; j < m; j += kCholThreads) {   // pivots -> diagonal of L
+        const double dj = sL[low_idx(j, j)];
+        sL[low_idx(j, j)] = sqrt((dj > 1e-14 * dmax) ? dj : (dmax > 0.0 ? dmax : 1.0));
+    }
+    __syncthreads();
     if (tid == 0 && (pass == 0 || s_bad)) *info = s_bad;
     // in-place inverse of L, last column first: with the trailing block already
     // inverted, column j of L^-1 is -(1/L_jj) Linv[j+1:, j+1:] L[j+1:, j];
-    // each row's dot product is split over S lanes of one wave
+    // each row's dot product is split over S lanes of one wave.  L_jj is read
+    // before the first barrier, so its inverse is written in the same phase
+    // as the column.
     for (int j = m - 1; j >= 0; --j) {
-        for (int i = j + 1 + tid; i < m; i += kCholThreads) colj[i] = sL[low_idx(i, j)];
-        __syncthreads();
+        double* cj = colj;
+        for (int i = j + 1 + tid; i < m; i += kCholThreads) cj[i] = sL[low_idx(i, j)];
         const double djj = 1.0 / sL[low_idx(j, j)];
+        __syncthreads();
         const int w = m - j - 1;
         if (w > 0) {
             int S = 64;
@@ -333,14 +340,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* _
             const int i = j + 1 + row;
             if (row < w) {
                 const double* Li = sL + low_idx(i, 0);
-                for (int l = j + 1 + sub; l <= i; l += S) acc += Li[l] * colj[l];
+                for (int l = j + 1 + sub; l <= i; l += S) acc += Li[l] * cj[l];
             }
             for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
             if (row < w && sub == 0) sL[low_idx(i, j)] = -djj * acc;
         }
-        __syncthreads();
         if (tid == 0) sL[low_idx(j, j)] = djj;
-        __syncthreads();
+        __syncthreads();   // colj is rewritten next
     }
     for (int e = tid; e < m * m; e += kCholThreads) {
         const int c = e / m, i = e % m;

@@ -42,6 +42,14 @@ struct Rot {
     double c, s;
 };
 
+// a pair slot of the current round: its players p < q and the offsets of
+// their rows in the packed triangle (element (i, j), i <= j, at roff(i) + j)
+struct alignas(8) PairSlot {
+    short p, q, rp, rq;
+};
+
+__device__ __forceinline__ int roff(int i, int n) { return i * n - (i * (i - 1)) / 2 - i; }
+
 // ------------------------------------------------------------------ LDS form
 // log_rot[round * npairs + slot], log_pq[round * npairs + slot] = p | q << 16;
 // *rounds = number of rounds performed.
@@ -50,8 +58,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
                                                                  Rot* __restrict__ log_rot, int* __restrict__ log_pq,
                                                                  int* __restrict__ rounds) {
     __shared__ double sA[kJacLdsN * (kJacLdsN + 1) / 2];
-    __shared__ double sc[kJacLdsN / 2], ss[kJacLdsN / 2];
-    __shared__ short sp[kJacLdsN / 2], sq[kJacLdsN / 2];
+    __shared__ Rot srot[kJacLdsN / 2];
+    __shared__ PairSlot spq[kJacLdsN / 2];
     __shared__ double s_red[kJacThreads / 64];
     __shared__ int s_rotated;
     const int tid = threadIdx.x;
@@ -70,21 +78,24 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
     double fro = 0.0;
     for (int w = 0; w < kJacThreads / 64; ++w) fro += s_red[w];
     const double abs_tol = 1e-15 * sqrt(fro);
-    // static list of this thread's blocks (pair slots P <= Q)
-    constexpr int kBlk = 5;   // 100 * 101 / 2 <= 5 * 1024
+    // static list of this thread's off-diagonal blocks (pair slots P < Q);
+    // the diagonal block of a pair is rotated by the thread that computes
+    // its rotation
+    constexpr int kBlk = 5;   // 100 * 99 / 2 <= 5 * 1024
     int blkP[kBlk], blkQ[kBlk];
-    const int nblk = npairs * (npairs + 1) / 2;
+    const int nblk = npairs * (npairs - 1) / 2;
 #pragma unroll
     for (int j = 0; j < kBlk; ++j) {
         int e = tid + j * kJacThreads, P = -1, Q = -1;
         if (e < nblk) {
             P = 0;
-            while (e >= npairs - P) { e -= npairs - P; ++P; }
-            Q = P + e;
+            while (e >= npairs - 1 - P) { e -= npairs - 1 - P; ++P; }
+            Q = P + 1 + e;
         }
         blkP[j] = P;
         blkQ[j] = Q;
     }
+    const bool odd = (n & 1) != 0;   // one player per round is the dummy index n
     int done_rounds = 0;
     for (int sweep = 0; sweep < kJacMaxSweeps; ++sweep) {
         if (tid == 0) s_rotated = 0;
@@ -94,8 +105,10 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
                 int p = rr_player(tid, round, N), q = rr_player(N - 1 - tid, round, N);
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
+                const int rp = roff(p, n), rq = roff(q, n);
                 if (q < n) {
-                    const double app = sA[tri_idx(p, p, n)], aqq = sA[tri_idx(q, q, n)], apq = sA[tri_idx(p, q, n)];
+                    const int ipp = rp + p, iqq = rq + q, ipq = rp + q;
+                    const double app = sA[ipp], aqq = sA[iqq], apq = sA[ipq];
                     const bool small = fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= abs_tol;
                     if (!small) {
                         const double theta = (aqq - app) / (2.0 * apq);
@@ -103,12 +116,16 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
                         c = 1.0 / sqrt(t * t + 1.0);
                         s = t * c;
                         s_rotated = 1;
+                        // the pair's own 2x2 block becomes R^T A R: no other
+                        // thread touches these three entries in this round
+                        sA[ipp] = c * c * app - 2.0 * c * s * apq + s * s * aqq;
+                        sA[iqq] = s * s * app + 2.0 * c * s * apq + c * c * aqq;
+                        sA[ipq] = 0.0;
                     }
                 }
-                sp[tid] = static_cast<short>(p);
-                sq[tid] = static_cast<short>(q);
-                sc[tid] = c;
-                ss[tid] = s;
+                srot[tid] = Rot{c, s};
+                spq[tid] = PairSlot{static_cast<short>(p), static_cast<short>(q), static_cast<short>(rp),
+                                    static_cast<short>(rq)};
                 const size_t li = (size_t)(done_rounds + round) * npairs + tid;
                 log_rot[li] = Rot{c, s};
                 log_pq[li] = p | (q << 16);
@@ -118,23 +135,18 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_lds_kernel(const double* _
             for (int j = 0; j < kBlk; ++j) {
                 const int P = blkP[j], Q = blkQ[j];
                 if (P < 0) continue;
-                const double c1 = sc[P], s1 = ss[P], c2 = sc[Q], s2 = ss[Q];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const int p1 = sp[P], q1 = sq[P], p2 = sp[Q], q2 = sq[Q];
-                const bool r1ok = q1 < n, r2ok = q2 < n;   // only q can be the dummy index (odd n)
-                if (P == Q) {
-                    if (!r1ok) continue;
-                    const int ipp = tri_idx(p1, p1, n), iqq = tri_idx(q1, q1, n), ipq = tri_idx(p1, q1, n);
-                    const double app = sA[ipp], aqq = sA[iqq], apq = sA[ipq];
-                    sA[ipp] = c1 * c1 * app - 2.0 * c1 * s1 * apq + s1 * s1 * aqq;
-                    sA[iqq] = s1 * s1 * app + 2.0 * c1 * s1 * apq + c1 * c1 * aqq;
-                    sA[ipq] = 0.0;
-                    continue;
+                const Rot r1 = srot[P], r2 = srot[Q];
+                if (r1.s == 0.0 && r2.s == 0.0) continue;
+                const double c1 = r1.c, s1 = r1.s, c2 = r2.c, s2 = r2.s;
+                const PairSlot a = spq[P], b = spq[Q];
+                // element (x, y) of the symmetric matrix from the packed upper triangle
+                auto at = [](int x, int rx, int y, int ry) { return x <= y ? rx + y : ry + x; };
+                const int i00 = at(a.p, a.rp, b.p, b.rp);
+                int i01 = at(a.p, a.rp, b.q, b.rq), i10 = at(a.q, a.rq, b.p, b.rp), i11 = at(a.q, a.rq, b.q, b.rq);
+                if (odd) {   // only q can be the dummy index
+                    if (b.q >= n) i01 = i11 = -1;
+                    if (a.q >= n) i10 = i11 = -1;
                 }
-                const int i00 = tri_idx(p1, p2, n);
-                const int i01 = r2ok ? tri_idx(p1, q2, n) : -1;
-                const int i10 = r1ok ? tri_idx(q1, p2, n) : -1;
-                const int i11 = (r1ok && r2ok) ? tri_idx(q1, q2, n) : -1;
                 const double x00 = sA[i00];
                 const double x01 = i01 >= 0 ? sA[i01] : 0.0;
                 const double x10 = i10 >= 0 ? sA[i10] : 0.0;
