@@ -299,7 +299,6 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const Y* Yv[3] = {static_cast<const Y*>(g.YA), static_cast<const Y*>(g.YB), static_cast<const Y*>(g.YC)};
     bool bad = false;
     const float cmask = g.compensated ? 1.0f : 0.0f;
-    constexpr bool kFoldO = !(M::EPL == 1 && KP == 112);
     // mA = Phi^T ybarA and mB = Phi^T ybarB ride along in Phi^T Phi when two
     // padding rows are free: the second operand of that product takes ybarA,
     // ybarB (the yfold rows) as "components" k and k+1, so G[i][k] = mA[i] and
@@ -307,8 +306,20 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     // the Phi copy, so G[k][.] and G[k+1][.] are zero as well.
     const bool mfold = (k + 2 <= KP);
 
-    // ---- master copy of Phi in registers: tile (mt, nt) holds a = row, i = column
-    f32x4 phi[TRK][TC], comp[TRK][TC];
+    // ---- master copy of Phi: tile (mt, nt) holds a = row, i = column.  In
+    // BF16 it lives in registers; in FP32 the LDS operand copy is exact, so it
+    // is the master copy itself and the registers go to the products.  The
+    // compensation terms stay in registers.
+    constexpr bool kPhiReg = M::EPL != 1;
+    f32x4 phi_r[kPhiReg ? TRK : 1][kPhiReg ? TC : 1], comp[TRK][TC];
+    auto phi_get = [&](int ti, int tj) -> f32x4 {
+        if constexpr (kPhiReg) {
+            return phi_r[ti][tj];
+        } else {
+            const int mt = wr + WR * ti, nt = wc + WC * tj;
+            return M::load4(&sm.phi[(nt * 16 + l16) * SP + mt * 16 + 4 * q]);
+        }
+    };
 #pragma unroll
     for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
@@ -327,7 +338,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 }
                 M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
             }
-            phi[ti][tj] = v;
+            if constexpr (kPhiReg) phi_r[ti][tj] = v;
             comp[ti][tj] = cv;
         }
     for (int e = tid; e < 3 * KP; e += kThreads) {
@@ -710,8 +721,6 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         // compensated addition at the end of the step then adds the whole
         // increment beta (D - kappa O) to the master copy.  The LDS operand
         // copies keep the old Phi, which every product of this step reads.
-        // (FP32 at KP = 112 keeps two compensated additions: there the fold
-        // made the register allocator spill more, and the step was slower.)
         if (!SCORE || train) {
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
@@ -719,18 +728,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
-                    if constexpr (kFoldO) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
-                    } else {   // a compensated addition of its own
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const float y = -f3 * oacc[ti][tj][r] - comp[ti][tj][r];
-                            const float tt = phi[ti][tj][r] + y;
-                            comp[ti][tj][r] = ((tt - phi[ti][tj][r]) - y) * cmask;
-                            phi[ti][tj][r] = tt;
-                        }
-                    }
+                    for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
                 }
             }
         }
@@ -970,8 +969,9 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                         const int mt = wr + WR * ti;
                         if (mt >= NTK) continue;
                         const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
+                        const f32x4 pv = phi_get(ti, tj);
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) part = fmaf(phi[ti][tj][r], fmaf(dacc[ti][tj][r], invB, ybc[r] * rv), part);
+                        for (int r = 0; r < 4; ++r) part = fmaf(pv[r], fmaf(dacc[ti][tj][r], invB, ybc[r] * rv), part);
                     }
                     score_t += static_cast<double>(nb) / static_cast<double>(n) * static_cast<double>(part * live[tj]);
                     continue;
@@ -985,16 +985,16 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     const int mt = wr + WR * ti;
                     if (mt >= NTK) continue;
                     const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
-                    f32x4 v = phi[ti][tj], cv = comp[ti][tj];
+                    f32x4 v = phi_get(ti, tj), cv = comp[ti][tj];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         // Kahan step; cmask = 0 turns it into the plain update
-                        const float y = fmaf(f1, dacc[ti][tj][r], f2 * ybc[r]) - cv[r];
+                        const float y = fmaf(f1, dacc[ti][tj][r], fmaf(f2, ybc[r], -cv[r]));
                         const float tt = v[r] + y;
                         cv[r] = ((tt - v[r]) - y) * cmask;
                         v[r] = tt;
                     }
-                    phi[ti][tj] = v;
+                    if constexpr (kPhiReg) phi_r[ti][tj] = v;
                     comp[ti][tj] = cv;
                     M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                 }
@@ -1005,9 +1005,12 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj)
 #pragma unroll
-                    for (int ti = 0; ti < TRK; ++ti)
+                    for (int ti = 0; ti < TRK; ++ti) {
+                        if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
+                        const f32x4 pv = phi_get(ti, tj);
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) bad |= !isfinite(phi[ti][tj][r]);
+                        for (int r = 0; r < 4; ++r) bad |= !isfinite(pv[r]);
+                    }
             }
             if (Snap != nullptr && train && s == g.spp - 1) {   // end of a pass: Phi to the snapshot of this pass
 #pragma unroll
@@ -1020,7 +1023,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int a = mt * 16 + 4 * q + r;
-                            if (a < k && i < k) Snap[(size_t)pass * k * k + (size_t)i * k + a] = phi[ti][tj][r];
+                            if (a < k && i < k) Snap[(size_t)pass * k * k + (size_t)i * k + a] = phi_get(ti, tj)[r];
                         }
                     }
             }
@@ -1077,7 +1080,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
             for (int r = 0; r < 4; ++r) {
                 const int a = mt * 16 + 4 * q + r;
                 if (a < k && i < k) {
-                    Phi[(size_t)i * k + a] = phi[ti][tj][r];
+                    Phi[(size_t)i * k + a] = phi_get(ti, tj)[r];
                     if (Comp) Comp[(size_t)i * k + a] = g.compensated ? comp[ti][tj][r] : 0.0f;
                 }
             }
