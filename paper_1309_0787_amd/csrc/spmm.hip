@@ -366,7 +366,41 @@ void plan_whiten_lds(WhitenPlan& p, const otm_csr& C, int k, int w_dtype) {
 constexpr int kM2Threads = 256;
 constexpr int kM2Unroll = 4;
 
+// Lane columns of a row of m <= 256 doubles: four per lane.  V2: pairs
+// (2 lane, 2 lane + 1) and (128 + 2 lane, 129 + 2 lane), one 16-byte load
+// each (m even, rows 16-byte aligned); otherwise lane + 64 u.  Each column
+// is summed over the entries in the same order either way.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <bool V2>
+__device__ __forceinline__ int m2_col(int lane, int u) {
+    return V2 ? 128 * (u >> 1) + 2 * lane + (u & 1) : lane + 64 * u;
+}
+template <bool V2>
+__device__ __forceinline__ void m2_load(const double* __restrict__ row, int lane, int m, bool ok, double (&v)[4]) {
+    if constexpr (V2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 128 * h + 2 * lane;
+            if (ok && c < m) {
+                const f64x2 t = *reinterpret_cast<const f64x2*>(row + c);
+                v[2 * h] = t[0];
+                v[2 * h + 1] = t[1];
+            } else {
+                v[2 * h] = 0.0;
+                v[2 * h + 1] = 0.0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = lane + 64 * u;
+            v[u] = (ok && c < m) ? row[c] : 0.0;
+        }
+    }
+}
+
 // T1[t,:] = w2_t sum_j C[t,j] S[j,:]; w1[t], w2[t] from the row sum when normalize
+template <bool V2>
 __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int normalize, const double* __restrict__ S,
                                                               int m, double* __restrict__ T1, double* __restrict__ w1,
                                                               double* __restrict__ w2, int32_t* info) {
@@ -393,12 +427,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
 #pragma unroll
             for (int x = 0; x < kM2Unroll; ++x) {
                 const bool ok = cc[x] >= 0 && cc[x] < C.n_cols;
-                const double* srow = S + (size_t)(ok ? cc[x] : 0) * m;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int col = lane + 64 * u;
-                    sv[x][u] = (ok && col < m) ? srow[col] : 0.0;
-                }
+                m2_load<V2>(S + (size_t)(ok ? cc[x] : 0) * m, lane, m, ok, sv[x]);
             }
 #pragma unroll
             for (int x = 0; x < kM2Unroll; ++x) {
@@ -406,7 +435,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
                 rs += vv[x];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (lane + 64 * u < m) acc[u] += vv[x] * sv[x][u];
+                    if (m2_col<V2>(lane, u) < m) acc[u] += vv[x] * sv[x][u];
             }
         }
         for (; p < e; ++p) {
@@ -414,12 +443,11 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
             if (c < 0 || c >= C.n_cols) continue;
             const double v = C.vals ? static_cast<double>(C.vals[p]) : 1.0;
             rs += v;
-            const double* srow = S + (size_t)c * m;
+            double sv[4];
+            m2_load<V2>(S + (size_t)c * m, lane, m, true, sv);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int col = lane + 64 * u;
-                if (col < m) acc[u] += v * srow[col];
-            }
+            for (int u = 0; u < 4; ++u)
+                if (m2_col<V2>(lane, u) < m) acc[u] += v * sv[u];
         }
         double a1 = 1.0, a2 = 1.0;
         if (normalize) {
@@ -434,7 +462,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int col = lane + 64 * u;
+            const int col = m2_col<V2>(lane, u);
             if (col < m) T1[(size_t)row * m + col] = a2 * acc[u];
         }
         if (lane == 0) {
@@ -445,6 +473,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass1_kernel(otm_csr C, int nor
 }
 
 // O[a,:] = sum_x CT[a,x] T1[x,:];  u[a] = sum_x CT[a,x] w2[x];  M1[a] = (1/n) sum_x CT[a,x] w1[x]
+template <bool V2>
 __global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const double* __restrict__ T1, int m,
                                                               const double* __restrict__ w1, const double* __restrict__ w2,
                                                               double inv_n, double* __restrict__ O, double* __restrict__ u,
@@ -472,12 +501,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const 
                 const int x = ok ? xx[y] : 0;
                 ww2[y] = w2[x];
                 ww1[y] = w1[x];
-                const double* trow = T1 + (size_t)x * m;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int col = lane + 64 * q;
-                    tv[y][q] = (ok && col < m) ? trow[col] : 0.0;
-                }
+                m2_load<V2>(T1 + (size_t)x * m, lane, m, ok, tv[y]);
             }
 #pragma unroll
             for (int y = 0; y < kM2Unroll; ++y) {
@@ -486,7 +510,7 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const 
                 sm += vv[y] * ww1[y];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (lane + 64 * q < m) acc[q] += vv[y] * tv[y][q];
+                    if (m2_col<V2>(lane, q) < m) acc[q] += vv[y] * tv[y][q];
             }
         }
         for (; p < e; ++p) {
@@ -495,16 +519,15 @@ __global__ __launch_bounds__(kM2Threads) void m2_pass2_kernel(otm_csr CT, const 
             const double v = CT.vals ? static_cast<double>(CT.vals[p]) : 1.0;
             su += v * w2[x];
             sm += v * w1[x];
-            const double* trow = T1 + (size_t)x * m;
+            double tv[4];
+            m2_load<V2>(T1 + (size_t)x * m, lane, m, true, tv);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int col = lane + 64 * q;
-                if (col < m) acc[q] += v * trow[col];
-            }
+            for (int q = 0; q < 4; ++q)
+                if (m2_col<V2>(lane, q) < m) acc[q] += v * tv[q];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int col = lane + 64 * q;
+            const int col = m2_col<V2>(lane, q);
             if (col < m) O[(size_t)row * m + col] = acc[q];
         }
         if (lane == 0) {
@@ -656,11 +679,21 @@ extern "C" int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, 
         int64_t b = (rows + waves_per_block - 1) / waves_per_block;
         return static_cast<int>(b < 1 ? 1 : (b > 4096 ? 4096 : b));
     };
-    hipLaunchKernelGGL(m2_pass1_kernel, dim3(blocks_for(n)), dim3(kM2Threads), 0, s, *C, normalize, S, k_tilde, T1, w1,
-                       w2, info);
+    // 16-byte row pieces when every row starts 16-byte aligned
+    const bool v2 = k_tilde % 2 == 0 && (reinterpret_cast<uintptr_t>(S) | reinterpret_cast<uintptr_t>(T1)) % 16 == 0;
+    if (v2)
+        hipLaunchKernelGGL(m2_pass1_kernel<true>, dim3(blocks_for(n)), dim3(kM2Threads), 0, s, *C, normalize, S, k_tilde,
+                           T1, w1, w2, info);
+    else
+        hipLaunchKernelGGL(m2_pass1_kernel<false>, dim3(blocks_for(n)), dim3(kM2Threads), 0, s, *C, normalize, S,
+                           k_tilde, T1, w1, w2, info);
     if ((st = check_launch("m2_pass1_kernel")) != OTM_OK) return st;
-    hipLaunchKernelGGL(m2_pass2_kernel, dim3(blocks_for(d)), dim3(kM2Threads), 0, s, *CT, T1, k_tilde, w1, w2,
-                       1.0 / n, O, u, M1);
+    if (v2)
+        hipLaunchKernelGGL(m2_pass2_kernel<true>, dim3(blocks_for(d)), dim3(kM2Threads), 0, s, *CT, T1, k_tilde, w1, w2,
+                           1.0 / n, O, u, M1);
+    else
+        hipLaunchKernelGGL(m2_pass2_kernel<false>, dim3(blocks_for(d)), dim3(kM2Threads), 0, s, *CT, T1, k_tilde, w1,
+                           w2, 1.0 / n, O, u, M1);
     if ((st = check_launch("m2_pass2_kernel")) != OTM_OK) return st;
     hipLaunchKernelGGL(weighted_colsum_partial_kernel, dim3(kWcsBlocks), dim3(kWcsThreads), 0, s, M1, S, d, k_tilde,
                        part);

@@ -695,9 +695,9 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti) {
                 const int mt = wr + WR * ti;
-                const int a = mt * 16 + l16;
                 if (mt < NTK) {
-                    // Phi[a][i], i = k0 + EPL q + e, from the component-major copy
+                    // Phi[a][i], a = 16 mt + lane % 16, i = k0 + EPL q + e, from the
+                    // component-major copy
                     fa[ti] = M::lds_t(&sm.phi[k0 * SP + mt * 16], SP, lane);
                 } else {
                     fa[ti] = M::zero_frag();
