@@ -285,6 +285,12 @@ def whiten(C: DeviceCSR, normalize: bool, W: torch.Tensor, y_dtype: int = F32, l
     column slice of a row-padded buffer; its row stride is passed as ldw."""
     d, k = W.shape
     w_ptr, ldw = _ptr_rows(W)
+    if out is not None:   # the row stride is the output's own
+        if out.dim() != 2 or out.shape[0] != C.n_rows or (ldy is not None and ldy != out.shape[1]):
+            raise ValueError(f"out must be {C.n_rows} x ldy, got {tuple(out.shape)} (ldy={ldy})")
+        if out.dtype != _TORCH_DTYPE[y_dtype]:
+            raise ValueError(f"out is {out.dtype}, y_dtype asks for {_TORCH_DTYPE[y_dtype]}")
+        ldy = out.shape[1]
     ldy = default_ldy(k) if ldy is None else ldy
     Y = out if out is not None else torch.empty((C.n_rows, ldy), dtype=_TORCH_DTYPE[y_dtype], device=W.device)
     ybar = torch.empty(k, dtype=torch.float32, device=W.device) if want_ybar else None
