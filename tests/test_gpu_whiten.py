@@ -82,6 +82,30 @@ def test_whiten_padded_row_stride(k, w_dt, y_dt):
         np.testing.assert_allclose(host(ybar), ybref, rtol=0, atol=1e-6 * np.abs(ybref).max())
 
 
+def test_whiten_into_given_output_uses_its_row_stride():
+    """An output buffer wider than the default row stride: the rows land at
+    its own stride with zero padding; a buffer of the wrong dtype or row
+    count is refused before any launch."""
+    g = synth.mmsb(n=800, k=4, alpha0=0.3, p=0.2, q=0.02, n_x=500, seed=3)
+    k = 20
+    W = f32_round(synth.projection(g.C.n_cols, k, seed=8))
+    Cd = csr_dev(g.C)
+    out = torch.full((g.C.n_rows, 40), float("nan"), dtype=torch.float32, device=dev())
+    Y, _ = otm.whiten(Cd, False, to_dev(W), y_dtype=otm.F32, out=out)
+    torch.cuda.synchronize()
+    assert Y.data_ptr() == out.data_ptr()
+    Yref, _ = oracle.whiten(g.C, W, normalize=False)
+    Yg = host(Y)
+    _check_rows(Yg, Yref, k, 2e-6)
+    assert np.all(Yg[:, k:] == 0.0)
+    with pytest.raises(ValueError):
+        otm.whiten(Cd, False, to_dev(W), y_dtype=otm.BF16, out=out)
+    with pytest.raises(ValueError):
+        otm.whiten(Cd, False, to_dev(W), y_dtype=otm.F32, out=out[:-1])
+    with pytest.raises(ValueError):
+        otm.whiten(Cd, False, to_dev(W), y_dtype=otm.F32, ldy=24, out=out)
+
+
 def test_whiten_document_views_padded_stride():
     """The document-workload shape (k = 50 FP32, W padded to 52 columns)."""
     inst = synth.lda(d=3000, k=5, alpha0=1.0, beta=0.1, n_docs=3001, mean_len=60.0, seed=11)
