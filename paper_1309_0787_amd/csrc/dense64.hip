@@ -22,18 +22,28 @@ namespace otm {
 namespace {
 
 // ------------------------------------------------------------------ gemm_tn
-constexpr int kTnTile = 32;
 constexpr int kTnRows = 16;
 
+// A block owns a TILE x TILE tile of C and one chunk of rows; a thread owns
+// the (TILE/16)^2 entries (p0 + ty + 16 i, q0 + tx + 16 j), TILE/32
+// multiply-adds per LDS read (64-tiles for the wide sketch products, 32-tiles
+// where 64 would leave most of a tile empty).  Each entry sums its chunk's
+// rows in order.
+template <int kTnTile>
 __global__ __launch_bounds__(256) void gemm_tn_partial_kernel(const double* __restrict__ A, int lda,
                                                               const double* __restrict__ B, int ldb, int d, int p,
                                                               int q, int chunk, double* __restrict__ part) {
+    constexpr int PT = kTnTile / 16;
     __shared__ double sA[kTnRows][kTnTile + 1];
     __shared__ double sB[kTnRows][kTnTile + 1];
     const int p0 = blockIdx.x * kTnTile, q0 = blockIdx.y * kTnTile;
     const int r0 = blockIdx.z * chunk, r1 = min(d, r0 + chunk);
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // thread owns (p0+2ty+{0,1}, q0+2tx+{0,1})
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[PT][PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i)
+#pragma unroll
+        for (int j = 0; j < PT; ++j) acc[i][j] = 0.0;
     for (int rb = r0; rb < r1; rb += kTnRows) {
         for (int e = threadIdx.x; e < kTnRows * kTnTile; e += 256) {
             const int rr = e / kTnTile, cc = e % kTnTile;
@@ -42,23 +52,26 @@ __global__ __launch_bounds__(256) void gemm_tn_partial_kernel(const double* __re
             sB[rr][cc] = (r < r1 && q0 + cc < q) ? B[(size_t)r * ldb + q0 + cc] : 0.0;
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 4
         for (int rr = 0; rr < kTnRows; ++rr) {
-            const double a0 = sA[rr][2 * ty], a1 = sA[rr][2 * ty + 1];
-            const double b0 = sB[rr][2 * tx], b1 = sB[rr][2 * tx + 1];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
+            double a[PT], b[PT];
+#pragma unroll
+            for (int i = 0; i < PT; ++i) a[i] = sA[rr][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < PT; ++j) b[j] = sB[rr][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < PT; ++i)
+#pragma unroll
+                for (int j = 0; j < PT; ++j) acc[i][j] += a[i] * b[j];
         }
         __syncthreads();
     }
     double* out = part + (size_t)blockIdx.z * p * q;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < PT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int pi = p0 + 2 * ty + i, qj = q0 + 2 * tx + j;
+        for (int j = 0; j < PT; ++j) {
+            const int pi = p0 + ty + 16 * i, qj = q0 + tx + 16 * j;
             if (pi < p && qj < q) out[(size_t)pi * q + qj] = acc[i][j];
         }
 }
@@ -82,8 +95,12 @@ int gemm_tn(const double* A, int lda, const double* B, int ldb, int d, int p, in
             hipStream_t s) {
     const int nch = tn_chunks(d);
     const int chunk = (d + nch - 1) / nch;
-    dim3 grid((p + kTnTile - 1) / kTnTile, (q + kTnTile - 1) / kTnTile, nch);
-    hipLaunchKernelGGL(gemm_tn_partial_kernel, grid, dim3(256), 0, s, A, lda, B, ldb, d, p, q, chunk, part);
+    if (p > 128 && q > 128)
+        hipLaunchKernelGGL(gemm_tn_partial_kernel<64>, dim3((p + 63) / 64, (q + 63) / 64, nch), dim3(256), 0, s, A, lda,
+                           B, ldb, d, p, q, chunk, part);
+    else
+        hipLaunchKernelGGL(gemm_tn_partial_kernel<32>, dim3((p + 31) / 32, (q + 31) / 32, nch), dim3(256), 0, s, A, lda,
+                           B, ldb, d, p, q, chunk, part);
     int st = check_launch("gemm_tn_partial_kernel");
     if (st != OTM_OK) return st;
     const int64_t m = (int64_t)p * q;
