@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -67,7 +69,9 @@ def counters_traffic():
 
 
 def cpu_baseline(inst, w):
-    """The FP64 oracle on the same workload (whole path, one decomposition)."""
+    """The FP64 oracle on the same workload (whole path, one decomposition).
+    Returns the baseline record and the oracle's results (for the per-result
+    errors of the GPU path)."""
     import numpy as np
     import oracle
     import synth
@@ -86,11 +90,109 @@ def cpu_baseline(inst, w):
     Y, ybar = oracle.whiten(inst.C, W, False)
     yb = np.stack([ybar] * 3)
     Phi = oracle.sgd_run(Y, Y, Y, yb, Phi0, perms, w["batch"], w["beta0"], w["beta_tau"], w["alpha0"])
-    oracle.recover_pi(Y, Phi, w["tau_pi"])
+    Pi = oracle.recover_pi(Y, Phi, w["tau_pi"])
     el = time.perf_counter() - t0
-    return {"value": inst.C.n_rows * w["passes"] / el, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"whole path once on the same graph (FP64): sketch q={w['q_power']}, whitener, whitening, "
-                      f"{w['passes']} STGD passes, memberships; {el:.1f} s"}
+    rec = {"value": inst.C.n_rows * w["passes"] / el, "unit": "samples/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"whole path once on the same graph (FP64): sketch q={w['q_power']}, whitener, whitening, "
+                     f"{w['passes']} STGD passes, memberships; {el:.1f} s"}
+    return rec, dict(W=W, Y=Y, ybar=yb, Phi=Phi, Pi=Pi, Phi0=Phi0, perms=perms)
+
+
+def _rel(a, b) -> float:
+    import numpy as np
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _host(t):
+    return t.detach().to("cpu", dtype=__import__("torch").float64).numpy()
+
+
+def errors_graph(res, ores, w, inst=None) -> dict:
+    """Error of each result of the benchmark step (BF16 W/Y and contractions,
+    FP64 sketch/whitener/post) against the FP64 oracle's whole path on the
+    same graph, projection, initial factors and permutations; then FP32 runs
+    with and without the compensated update on the oracle's rows (FP32
+    rounded) against the oracle run on the same rows."""
+    import numpy as np
+    import torch
+    from paper_1309_0787_amd import otm
+    k, n = w["k"], ores["Y"].shape[0]
+    Yg = _host(res.Y[0])[:, :k]
+    row_err = np.linalg.norm(Yg - ores["Y"], axis=1) / np.maximum(np.linalg.norm(ores["Y"], axis=1), 1e-300)
+    Pi_g = _host(res.Pi)
+    out = {"W": _rel(_host(res.W), ores["W"]),
+           "Y": _rel(Yg, ores["Y"]), "Y_row_max": float(row_err.max()),
+           "Phi": _rel(_host(res.Phi[0]).T, ores["Phi"]),
+           "Pi": _rel(Pi_g, ores["Pi"]), "Pi_max_abs": float(np.abs(Pi_g - ores["Pi"]).max()),
+           "precision": "W FP64 (BF16 copy for the SpMM), Y BF16, STGD BF16 operands / FP32 accumulate and "
+                        "compensated FP32 master, Pi FP64 arithmetic; Y and Phi include the BF16 rounding"}
+    dev = res.W.device
+    ldy = otm.default_ldy(k)
+    Y32 = torch.zeros((n, ldy), dtype=torch.float32, device=dev)
+    Y32[:, :k] = torch.as_tensor(ores["Y"], dtype=torch.float32, device=dev)
+    yb3 = torch.as_tensor(ores["ybar"].astype(np.float32).reshape(-1), device=dev)
+    permd = torch.as_tensor(ores["perms"], device=dev)
+    for comp in (True, False):
+        p = otm.SgdParams(k=k, batch=w["batch"], passes=w["passes"], y_dtype=otm.F32, compensated=comp,
+                          alpha0=w["alpha0"], beta0=w["beta0"], beta_tau=w["beta_tau"], ldy=ldy)
+        Phi = torch.as_tensor(ores["Phi0"].T.copy(), dtype=torch.float32, device=dev)[None].contiguous()
+        otm.sgd_run(p, n, Y32, Y32, Y32, yb3, permd, Phi)
+        torch.cuda.synchronize()
+        out["Phi_fp32_" + ("compensated" if comp else "plain")] = _rel(_host(Phi[0]).T, ores["Phi"])
+    out["fp32_steps"] = w["passes"] * ((n + w["batch"] - 1) // w["batch"])
+    if inst is not None:   # the method's own limit on this graph: the oracle's memberships against the planted
+        out["recovery_error_oracle"] = recovery_error(torch.as_tensor(ores["Pi"]), inst.pi[inst.X])
+        out["recovery_error_gpu"] = recovery_error(res.Pi, inst.pi[inst.X])
+    return out
+
+
+DOCS = dict(k=50, alpha0=1.0, q_power=3, batch=100, passes=50, beta0=1e-3, beta_tau=2500.0)
+
+
+def errors_documents(inst) -> dict:
+    """The document workload (d = 10000, k = 50, 1e5 documents, three views,
+    FP32 W/Y/STGD, FP64 sketch/whitener/topics) through the whole path on the
+    GPU, each result against the FP64 oracle's path on the same inputs:
+    W, the three views' Y, Phi, the topic-word matrix and the weights."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from paper_1309_0787_amd import otm, pipeline
+    w = DOCS
+    dev = torch.device("cuda:0")
+    k, n = w["k"], inst.C.n_rows
+    S = synth.projection(inst.C.n_cols, 2 * k, seed=1)
+    perms = synth.permutations(n, w["passes"], seed=2)
+    Phi0 = synth.initial_factors(k, seed=4)
+    views = [otm.DeviceCSR.from_host(v, dev) for v in inst.views]
+    C, CT = otm.DeviceCSR.from_host(inst.C, dev), otm.DeviceCSR.from_host(inst.CT, dev)
+    cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=True, q_power=w["q_power"], y_dtype=otm.F32,
+                             batch=w["batch"], passes=w["passes"], beta0=w["beta0"], beta_tau=w["beta_tau"],
+                             topics=True)
+    Phi = torch.as_tensor(Phi0.T.copy(), dtype=torch.float32, device=dev)[None].contiguous()
+    tm = pipeline.Timer(True)
+    res = pipeline.fit(views, C, CT, torch.as_tensor(S, device=dev), Phi, torch.as_tensor(perms, device=dev), cfg,
+                       timer=tm)
+    torch.cuda.synchronize()
+    gpu_ms = {a: round(b, 3) for a, b in tm.spans_ms().items()}
+    t0 = time.perf_counter()
+    Q, O = oracle.power_sketch(inst.C, S, w["alpha0"], True, w["q_power"])
+    Wo, _ = oracle.whitener_rsvd(O, Q, k)
+    Ys = [oracle.whiten(v, Wo, True) for v in inst.views]
+    yb = np.stack([y[1] for y in Ys])
+    Phio = oracle.sgd_run(Ys[0][0], Ys[1][0], Ys[2][0], yb, Phi0, perms, w["batch"], w["beta0"], w["beta_tau"],
+                          w["alpha0"])
+    muo, aho, _ = oracle.unwhiten_topics(Wo, Phio)
+    el = time.perf_counter() - t0
+    mug = _host(res.mu)
+    return {"workload": f"documents d={inst.C.n_cols}, k={k}, n={n}, three views, FP32, {w['passes']} passes",
+            "W": _rel(_host(res.W), Wo),
+            "Y": max(_rel(_host(res.Y[i])[:, :k], Ys[i][0]) for i in range(3)),
+            "Phi": _rel(_host(res.Phi[0]).T, Phio),
+            "mu": _rel(mug, muo), "mu_max_abs": float(np.abs(mug - muo).max()),
+            "alpha_hat": _rel(_host(res.alpha_hat), aho),
+            "gpu_stage_ms": gpu_ms, "oracle_s": round(el, 2)}
 
 
 # beta0 3e-4: at 1e-3 the three-view problems with k = 100 and alpha0 = 1 diverge
@@ -170,10 +272,181 @@ def bench_batched(steps: int, warmup: int) -> dict:
     }
 
 
-WARM = dict(instances=8000, epochs=15, batch=256, lr=1e-3, exact_share=0.8, sampled_n=2000)
+WARM = dict(instances=50000, exact_share=0.8, sampled_n=2000, epochs=6, batch=256, lr=1e-3, heldout=1000)
 
 
-def bench_spmm(reps: int = 20) -> dict:
+def train_warm_start(inst, pool_res, w) -> tuple:
+    """The learned warm start trained on instances from the three workloads'
+    generators (cfg 5): 80% exact-moment instances of block models drawn by
+    the small graph, document and large graph generators (k = 10, 50, 100),
+    20% sampled instances: seeded subsets of 2000 whitened rows of the
+    benchmark graph with its planted directions as targets."""
+    import torch
+    from paper_1309_0787_amd import otm
+    from paper_1309_0787_amd import warmstart as pws
+    dev = torch.device("cuda:0")
+    cfg = WARM
+    k = w["k"]
+    # planted directions of the benchmark graph in its whitened coordinates:
+    # u_i = sqrt(ahat_i) W^T F_i, F = Pi_A^T P^T, ahat = 1/k
+    W = pool_res.W.double().cpu().numpy()
+    F = inst.pi[inst.A] @ inst.P.T
+    U = (W.T @ F) / np.sqrt(k)
+    Yp = pool_res.Y[0].float()
+    pool = {"Y": Yp, "U": U, "lam": np.full(k, np.sqrt(k)), "alpha0": w["alpha0"]}
+    g = np.random.default_rng(0)
+    fams = list(pws.FAMILIES)
+    specs = []
+    for i in range(cfg["instances"]):
+        if g.random() < cfg["exact_share"]:
+            specs.append(dict(kind="exact", family=fams[int(g.integers(3))], seed=5000 + i))
+        else:
+            specs.append(dict(kind="sampled", seed=5000 + i, n=cfg["sampled_n"]))
+    t0 = time.perf_counter()
+    tr = pws.build_generated(specs, dev, sampled_pool=pool)
+    warm = pws.WarmStart(dev, seed=3)
+    _, _, X, tgt, _ = warm.prepare(tr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = warm.train(X, tgt, tr.ks, epochs=cfg["epochs"], batch=cfg["batch"], lr=cfg["lr"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"train_instances": len(specs), "exact": sum(s["kind"] == "exact" for s in specs),
+            "epochs": cfg["epochs"], "build_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+            "adam_steps": len(losses), "final_loss": float(np.mean(losses[-20:]))}
+    del X, tgt, tr
+    return warm, info
+
+
+def bench_heldout(warm) -> dict:
+    """SGD iterations to R <= 1e-3 on 1000 held-out exact-moment instances
+    (disjoint seeds; the three generators, k = 10, 50, 100), FP32, from the
+    warm start and from random orthonormal factors, all instances of an arm in
+    one batched launch per chunk of passes; R after each chunk from the
+    batched kernel's restart score (R = 1 + score / ||T||^2, ||T||^2 =
+    sum lambda^2)."""
+    import torch
+    from paper_1309_0787_amd import otm
+    from paper_1309_0787_amd import warmstart as pws
+    import synth
+    dev = torch.device("cuda:0")
+    cnt = WARM["heldout"]
+    fams = list(pws.FAMILIES)
+    g = np.random.default_rng(1)
+    specs = [dict(kind="exact", family=fams[int(g.integers(3))], seed=900000 + i) for i in range(cnt)]
+    hs = pws.build_generated(specs, dev)
+    Pw = pws.warm_factors_batch(warm, hs)
+    ks = hs.ks.cpu().numpy()
+    rows, tnorm = [], []
+    for i, sp in enumerate(specs):
+        Y, _, lam = pws.generated_exact_instance(sp["family"], sp["seed"])
+        k = Y.shape[0]
+        ldy = otm.default_ldy(k)
+        Yd = torch.zeros((k, ldy), dtype=torch.float32, device=dev)
+        Yd[:, :k] = torch.as_tensor(Y, device=dev)
+        rows.append((Yd, torch.stack([Yd[:, :k].mean(0)] * 3).contiguous(), k))
+        tnorm.append(float(np.sum(lam ** 2)))
+    tnorm = np.asarray(tnorm)
+    chunks = [25, 25, 50, 100, 200, 400, 400, 800]
+    beta0 = 0.02
+    out = {}
+    for arm in ("random", "warm"):
+        if arm == "warm":
+            phis = [Pw[i, :rows[i][2] ** 2].reshape(1, rows[i][2], rows[i][2]).clone() for i in range(cnt)]
+        else:
+            phis = [torch.as_tensor(synth.initial_factors(rows[i][2], seed=7, restart=i).T.copy(), dtype=torch.float32,
+                                    device=dev)[None].contiguous() for i in range(cnt)]
+        done = np.full(cnt, -1)
+        steps = 0
+        ms = 0.0
+        for c in chunks:
+            problems = [otm.Problem(Y, Y, Y, yb, phis[i], k, 0.0) for i, (Y, yb, k) in enumerate(rows)]
+            p = otm.SgdParams(k=1, batch=100, passes=c, y_dtype=otm.F32, beta0=beta0, beta_tau=1e12)
+            run = otm.BatchedRun(problems, 1, p)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            steps += c
+            R = 1.0 + np.array([float(sc.item()) for sc in run.scores]) / tnorm
+            newly = (done < 0) & (R <= 1e-3)
+            done[newly] = steps
+            phis = [ph.clone() for ph in run.Phi]
+            run.close()
+        ok = done > 0
+        out[arm] = {"success_rate": float(ok.mean()),
+                    "median_steps_to_1e-3": float(np.median(done[ok])) if ok.any() else None,
+                    "success_by_k": {int(kk): float(ok[ks == kk].mean()) for kk in sorted(set(ks.tolist()))},
+                    "gpu_ms": round(ms, 1)}
+    out["workload"] = (f"{cnt} held-out exact-moment instances (block-model limits of the three generators, k in "
+                       f"{{10, 50, 100}}), FP32, full batch, beta {beta0}, up to {sum(chunks)} steps; "
+                       f"iterations counted at chunk ends {list(np.cumsum(chunks))}")
+    return out
+
+
+def bench_time_to_loss(inst, C, CT, S, Phi_init, w, warm, warm_info) -> dict:
+    """Time to the converged loss on the benchmark graph, four arms:
+    {FP32, BF16} x {random: best of 8 random restarts in one launch; warm: the
+    learned warm start as restart 0 beside 7 random restarts}, 100 passes
+    each.  R of every restart at every pass end from snapshots (outside the
+    timed stages), all against the FP32 arm's tensor.  Threshold: the best
+    converged R over the arms plus 1e-3; an arm's time to loss is its
+    prefix (sketch, whitener, whitening, warm start) plus its STGD time up to
+    the first pass whose best restart reaches the threshold.  Memberships of
+    each arm's best restart against the planted ones."""
+    import torch
+    from paper_1309_0787_amd import otm, pipeline
+    import synth
+    dev = torch.device("cuda:0")
+    k, R, passes = w["k"], 8, 100
+    n = inst.C.n_rows
+    perms = torch.as_tensor(np.stack([synth.permutations(n, passes, seed=2, sub=r) for r in range(R)]), device=dev)
+    Phi_rand = torch.as_tensor(np.stack([synth.initial_factors(k, seed=4, restart=r).T for r in range(R)]),
+                               dtype=torch.float32, device=dev).contiguous()
+    runs, T_ref = {}, None
+    pi_true = inst.pi[inst.X]
+    for name, ydt, use_warm in (("fp32_random", otm.F32, False), ("fp32_warm", otm.F32, True),
+                                ("bf16_random", otm.BF16, False), ("bf16_warm", otm.BF16, True)):
+        cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=ydt,
+                                 batch=w["batch"], passes=passes, beta0=w["beta0"], beta_tau=w["beta_tau"],
+                                 tau_pi=w["tau_pi"], restarts=R)
+        Phi = Phi_rand.clone()
+        tm = pipeline.Timer(True)
+        res = pipeline.fit([C], C, CT, S, Phi, perms, cfg, snapshots=True, timer=tm, warm=warm if use_warm else None)
+        torch.cuda.synchronize()
+        if T_ref is None:
+            T_ref = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
+        Rs = otm.residual(T_ref, res.snapshots.reshape(-1, k, k).contiguous()).cpu().numpy().reshape(R, passes)
+        best_r = int(np.argmin(Rs[:, -1]))
+        Pi = otm.recover_pi(res.Y[0], k, res.Phi[best_r], tau=w["tau_pi"])
+        runs[name] = dict(stages=tm.spans_ms(), Rs=Rs, best=best_r, rec=recovery_error(Pi, pi_true))
+    r_inf = min(float(r["Rs"][:, -1].min()) for r in runs.values())
+    thr = r_inf + 1e-3
+    out = {"threshold": thr, "R_inf": r_inf, "passes": passes, "restarts": R}
+    for name, r in runs.items():
+        best_by_pass = r["Rs"].min(axis=0)
+        hit = np.nonzero(best_by_pass <= thr)[0]
+        pz = int(hit[0]) + 1 if hit.size else None
+        st = r["stages"]
+        prefix = st.get("sketch", 0) + st.get("whitener", 0) + st.get("whiten", 0) + st.get("warm", 0)
+        out[name] = {"time_to_loss_ms": (prefix + st["stgd"] * pz / passes) if pz else None,
+                     "passes_to_loss": pz, "R_final_best": float(r["Rs"][:, -1].min()),
+                     "R_pass1_best": float(r["Rs"][:, 0].min()), "R_final_warm_restart": float(r["Rs"][0, -1]),
+                     "best_restart": r["best"], "stgd_ms": round(st["stgd"], 2), "prefix_ms": round(prefix, 2),
+                     "recovery_error": r["rec"]}
+    def ratio(a, b):
+        x, y = out[a]["time_to_loss_ms"], out[b]["time_to_loss_ms"]
+        return (x / y) if (x and y) else None
+    out["speedup_warm_fp32"] = ratio("fp32_random", "fp32_warm")
+    out["speedup_warm_bf16"] = ratio("bf16_random", "bf16_warm")
+    out["speedup_bf16_warm_vs_fp32_random"] = ratio("fp32_random", "bf16_warm")
+    out["warm_start"] = warm_info
+    return out
+
+
+def bench_spmm(inst, reps: int = 20) -> dict:
     """Whitening SpMM on the document workload (d = 10000, k = 50, 1e5
     documents of Poisson(200) tokens, three views, FP32 counts, FP32 W and Y):
     the HBM-bound case.  W is a seeded Gaussian d x k matrix (the values do not
@@ -186,9 +459,6 @@ def bench_spmm(reps: int = 20) -> dict:
     import synth
 
     dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    inst = synth.make("lda_medium")
-    t_gen = time.perf_counter() - t0
     k, d, n = 50, inst.C.n_cols, inst.C.n_rows
     views = [otm.DeviceCSR.from_host(v, dev) for v in inst.views]
     ldw = otm.default_ldw(k, otm.F32)
@@ -215,8 +485,7 @@ def bench_spmm(reps: int = 20) -> dict:
             "ms_per_three_views": ms, "algorithmic_bytes": algo,
             "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": achieved / PEAK_HBM},
-            "w_gather_bytes": nnz * ldw * 4, "w_gather_tb_per_s": nnz * ldw * 4 / (ms * 1e-3) / 1e12,
-            "generation_s": round(t_gen, 2)}
+            "w_gather_bytes": nnz * ldw * 4, "w_gather_tb_per_s": nnz * ldw * 4 / (ms * 1e-3) / 1e12}
 
 
 def recovery_error(Pi: "torch.Tensor", pi_true: "np.ndarray") -> float:
@@ -300,6 +569,122 @@ def bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w) -> dict:
     out["warm_start"] = {"train_instances": ws_cfg["instances"], "epochs": ws_cfg["epochs"],
                          "build_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
                          "final_loss": float(np.mean(losses[-10:])), "adam_steps": len(losses)}
+    return out
+
+
+def _validation_record(Pi_hat, pi_true) -> dict:
+    """Recovery ratio and error of Section 5.2 (p-value matching, BH-adjusted,
+    threshold 0.01) of estimated memberships (k x n, GPU) against the planted
+    ones (n x k host), computed by the library's validation kernels."""
+    import torch
+    from paper_1309_0787_amd import otm
+    P = torch.as_tensor(pi_true.T.astype(np.float32), device=Pi_hat.device).contiguous()
+    V = otm.validate(Pi_hat.float().contiguous(), P, 0.01)
+    sc = V.scores.cpu().numpy()
+    return {"recovery_ratio": float(sc[0]), "error": float(sc[1]), "edges": int(V.edges.sum().item())}
+
+
+def bench_validation_small() -> dict:
+    """The small graph (n = 1000, X/A 500/500, k = 10, alpha0 = 0.1, p = 0.3,
+    q = 0.05): whole path on the GPU (FP32), 8 restarts in one launch, the
+    lowest residual kept; R and E of its memberships, and the same for the
+    oracle's path."""
+    import torch
+    import oracle
+    import synth
+    from paper_1309_0787_amd import otm, pipeline
+    dev = torch.device("cuda:0")
+    g = synth.make("mmsb_small")
+    k, a0, R = 10, 0.1, 8
+    S = synth.projection(g.C.n_cols, 2 * k, seed=1)
+    n = g.C.n_rows
+    perms = synth.permutations(n, 50, seed=2)
+    Phi0 = np.stack([synth.initial_factors(k, seed=3, restart=r).T for r in range(R)])
+    C, CT = otm.DeviceCSR.from_host(g.C, dev), otm.DeviceCSR.from_host(g.CT, dev)
+    cfg = pipeline.FitConfig(k=k, alpha0=a0, q_power=3, y_dtype=otm.F32, batch=100, passes=50, beta0=0.05,
+                             beta_tau=500.0, restarts=R, tau_pi=0.1)
+    Phi = torch.as_tensor(Phi0, dtype=torch.float32, device=dev).contiguous()
+    res = pipeline.fit([C], C, CT, torch.as_tensor(S, device=dev), Phi, torch.as_tensor(perms, device=dev), cfg)
+    T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, a0)
+    Rs = otm.residual(T, res.Phi).cpu().numpy()
+    best = int(np.argmin(Rs))
+    Pi = otm.recover_pi(res.Y[0], k, res.Phi[best], tau=0.1)
+    out = {"workload": "MMSB n=1000 (X/A 500/500) k=10 alpha0=0.1 p=0.3 q=0.05, FP32, 50 passes, best of 8 restarts",
+           "R_best": float(Rs[best]), "gpu": _validation_record(Pi, g.pi[g.X]),
+           "recovery_error": recovery_error(Pi, g.pi[g.X])}
+    Q, O = oracle.power_sketch(g.C, S, a0, False, 3)
+    W, _ = oracle.whitener_rsvd(O, Q, k)
+    Y, yb = oracle.whiten(g.C, W, False)
+    yb3 = np.stack([yb] * 3)
+    Tn = oracle.whitened_tensor(Y, Y, Y, yb3, a0)
+    best_o, bR = None, np.inf
+    for r in range(R):
+        P_o = oracle.sgd_run(Y, Y, Y, yb3, Phi0[r].T, perms, 100, 0.05, 500.0, a0)
+        Rr = oracle.residual(Tn, P_o)
+        if Rr < bR:
+            best_o, bR = P_o, Rr
+    Pi_o = oracle.recover_pi(Y, best_o, 0.1)
+    out["oracle"] = _validation_record(torch.as_tensor(Pi_o, dtype=torch.float32, device=dev), g.pi[g.X])
+    out["oracle"]["R_best"] = float(bR)
+    return out
+
+
+def bench_four_partition(w) -> dict:
+    """Section 2.2's four-partition estimator (nodes split into X/A/B/C,
+    transition matrices through the randomized pseudo-inverse) on the
+    benchmark's graph model (n = 1e5, k = 100, BF16 views and STGD), and on a
+    denser graph (n = 2e4, k = 5, FP32) beside the single-leaf-set path on
+    the same X and A blocks: stage times, residual, memberships."""
+    import time as _t
+    import torch
+    import synth
+    from paper_1309_0787_amd import otm, pipeline
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, n, k, a0, p, q, ydt, passes in (("large", w["n"], w["k"], w["alpha0"], w["p"], w["q"], otm.BF16, 50),
+                                             ("dense", 20000, 5, 0.5, 0.3, 0.02, otm.F32, 50)):
+        t0 = _t.perf_counter()
+        g = synth.mmsb_four(n, k, a0, p, q)
+        t_gen = _t.perf_counter() - t0
+        B = g.blocks
+        G = otm.DevicePartition.from_blocks(B, dev)
+        nA, nB, nC = (B[("X", s)].n_cols for s in "ABC")
+        nx = B[("X", "A")].n_rows
+        S = torch.as_tensor(synth.projection(nA, k, seed=1), device=dev)
+        SB = torch.as_tensor(synth.projection(nB, 2 * k, seed=11), device=dev)
+        SC = torch.as_tensor(synth.projection(nC, 2 * k, seed=12), device=dev)
+        perms = torch.as_tensor(synth.permutations(nx, passes, seed=2), device=dev)
+        Phi0 = torch.as_tensor(synth.initial_factors(k, seed=4).T.copy(), dtype=torch.float32, device=dev)[None]
+        cfg = pipeline.FitConfig(k=k, alpha0=a0, q_power=1, y_dtype=ydt, batch=100, passes=passes, beta0=1e-3,
+                                 beta_tau=2500.0, tau_pi=0.1)
+        blocks = [otm.DeviceCSR.from_host(B[(s, "A")], dev) for s in "BC"]
+        Phi = Phi0.clone()
+        pipeline.fit_four(G, S, SB, SC, Phi, perms, cfg, q_pinv=1, node_blocks=blocks)   # warm-up
+        Phi = Phi0.clone()
+        tm = pipeline.Timer(True)
+        res = pipeline.fit_four(G, S, SB, SC, Phi, perms, cfg, q_pinv=1, node_blocks=blocks, timer=tm)
+        torch.cuda.synchronize()
+        T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, a0)
+        rec = {"workload": f"MMSB n={n} k={k} alpha0={a0} p={p} q={q}, X/A/B/C quarters, "
+                           f"{'BF16' if ydt == otm.BF16 else 'FP32'}, {passes} passes",
+               "stage_ms": {a: round(b, 3) for a, b in tm.spans_ms().items()},
+               "R": float(otm.residual(T, res.Phi[0]).item()), "nonfinite": int(res.nonfinite.item()),
+               "recovery_error_X": recovery_error(res.Pi, g.pi[g.sets["X"]]),
+               "recovery_error_B": recovery_error(res.Pi_nodes[0], g.pi[g.sets["B"]]),
+               "validation_X": _validation_record(res.Pi, g.pi[g.sets["X"]]),
+               "generation_s": round(t_gen, 2)}
+        if name == "dense":   # the single-leaf-set path on the same X, A blocks
+            C, CT = G.XA, G.AX
+            cfg1 = pipeline.FitConfig(k=k, alpha0=a0, q_power=3, y_dtype=ydt, batch=100, passes=passes, beta0=1e-3,
+                                      beta_tau=2500.0, tau_pi=0.1)
+            Phi = Phi0.clone()
+            S2 = torch.as_tensor(synth.projection(nA, 2 * k, seed=1), device=dev)
+            r1 = pipeline.fit([C], C, CT, S2, Phi, perms, cfg1, pi_view=0)
+            T1 = otm.tensor_form(r1.Y[0], r1.Y[1], r1.Y[2], k, r1.ybar3, a0)
+            rec["single_leaf_set"] = {"R": float(otm.residual(T1, r1.Phi[0]).item()),
+                                      "recovery_error_X": recovery_error(r1.Pi, g.pi[g.sets["X"]])}
+        out[name] = rec
+        del G, B, g
     return out
 
 
@@ -407,22 +792,40 @@ def main():
         "sgd_us_per_step": sgd_ms * 1e3 / (w["passes"] * ((n + w["batch"] - 1) // w["batch"])),
         "generation_s": round(t_gen, 2),
     }
+    print("bench: validation (recovery ratio, error) and the four-partition estimator", file=sys.stderr, flush=True)
+    out["validation"] = {"large": dict(_validation_record(res.Pi, inst.pi[inst.X]),
+                                       recovery_error=recovery_error(res.Pi, inst.pi[inst.X])),
+                         "small": bench_validation_small()}
+    out["four_partition"] = bench_four_partition(w)
     if args.quality:
         T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
         out["quality"] = {"residual": float(otm.residual(T, res.Phi[0]).item()),
                           "nonfinite": int(res.nonfinite.item())}
     if not args.no_time_to_loss:
-        print("bench: time to loss, BF16 + warm start against FP32", file=sys.stderr, flush=True)
-        out["time_to_loss"] = bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w)
+        print("bench: warm-start training (instances of the three generators)", file=sys.stderr, flush=True)
+        warm, warm_info = train_warm_start(inst, res, w)
+        print("bench: held-out instances, warm against random", file=sys.stderr, flush=True)
+        out["warm_start_heldout"] = bench_heldout(warm)
+        print("bench: time to loss, four arms", file=sys.stderr, flush=True)
+        out["time_to_loss"] = bench_time_to_loss(inst, C, CT, S, Phi_init, w, warm, warm_info)
+    docs = None
+    if not args.no_spmm or not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        docs = synth.make("lda_medium")
+        print(f"bench: document workload generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_spmm:
         print("bench: whitening SpMM on the document workload", file=sys.stderr, flush=True)
-        out["spmm"] = bench_spmm()
+        out["spmm"] = bench_spmm(docs)
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1)
     if not args.no_cpu_baseline:
         print("bench: oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, w)
+        out["cpu_baseline"], ores = cpu_baseline(inst, w)
+        print("bench: per-result errors against the oracle (graph)", file=sys.stderr, flush=True)
+        out["error_vs_oracle"] = {"graph": errors_graph(res, ores, w, inst)}
+        print("bench: per-result errors against the oracle (documents)", file=sys.stderr, flush=True)
+        out["error_vs_oracle"]["documents"] = errors_documents(docs)
     print(json.dumps(out), flush=True)
 
 

@@ -96,6 +96,25 @@ int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, double alph
                  const double* S, int32_t k_tilde, double* O, int32_t* info,
                  void* ws, size_t ws_bytes, otm_stream stream);
 
+/* M2 applied to a column-selection projection with random signs (Section
+ * 4.2: for a sparse M2 the projection S in {0, +-1}^(d x k_tilde) selects
+ * k_tilde columns): S[r_j, j] = s_j, so
+ *   O[:, j] = s_j M2[:, r_j]
+ *           = s_j [(alpha0+1)/n (sum_t w2_t c_t[r_j] c_t - u[r_j] e_(r_j)) - alpha0 M1 M1[r_j]],
+ * u = C^T w2, M1 and w1, w2 as in otm_m2_apply.  Only the samples with
+ * c_t[r_j] != 0 (row r_j of CT) and their rows are read.  sel_rows: k_tilde
+ * int32 rows in [0, d); sel_signs: k_tilde FP64 (+-1).  O: d x k_tilde FP64.
+ * info: device int32, 0 on success, 1 as in otm_m2_apply, 2 when a selected
+ * row lies outside [0, d) (that column is left 0).  Deterministic: each
+ * column's sums run over the samples in their stored order. */
+size_t otm_m2_apply_select_workspace(int32_t n, int32_t d);
+int otm_m2_apply_select(const otm_csr* C, const otm_csr* CT, int normalize, double alpha0, const int32_t* sel_rows,
+                        const double* sel_signs, int32_t k_tilde, double* O, int32_t* info, void* ws, size_t ws_bytes,
+                        otm_stream stream);
+/* The d x k_tilde FP64 matrix of a column selection (for otm_whitener's S). */
+int otm_selection_dense(const int32_t* sel_rows, const double* sel_signs, int32_t d, int32_t k_tilde, double* S,
+                        otm_stream stream);
+
 /* ---- a2: randomized whitener (Section 3.1; Section 4.2, "Randomized
  * Tall-thin SVD" and its tall-thin QR variant) -----------------------------
  * From O = M2 S (d x k_tilde) and S (d x k_tilde), FP64:
@@ -129,6 +148,78 @@ int otm_whitener(const double* O, const double* S, int32_t d, int32_t k_tilde, i
 size_t otm_orthonormalize_workspace(int32_t d, int32_t m);
 int otm_orthonormalize(const double* Y, int32_t d, int32_t m, double* Q, int32_t* info,
                        void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- four-partition graph moments (Section 2.2: transition matrices of
+ * Eq. transitionMat, moments of Eqs. 1moment_graph / 2moment_graph; Section
+ * 4.1: products in factored form; Section 4.2: algorithm "Randomized
+ * Pseudoinverse") ----------------------------------------------------------
+ * The nodes are split into the samples X and the leaf sets A, B, C;
+ * Pairs(Y1, Y2) = (1/n_X) G[X, Y1]^T G[X, Y2].  The blocks of the adjacency
+ * matrix the estimator reads, each a CSR with its transpose: */
+typedef struct {
+    otm_csr XA, XB, XC;   /* G[X, A], G[X, B], G[X, C]: n_X x n_A, n_X x n_B, n_X x n_C */
+    otm_csr AX, BX, CX;   /* G[A, X], G[B, X], G[C, X]: the transposes, same entries */
+} otm_partition;
+
+/* out (n1 x m) = Pairs(Y1, Y2) V = (1/n_X) G1T (G2 V) for G1T = G[Y1, X]
+ * (n1 x n_X), G2 = G[X, Y2] (n_X x n2) and V (n2 x m FP64 row-major),
+ * 1 <= m <= 256.  ws: otm_pairs_apply_workspace(n_X, m) bytes. */
+size_t otm_pairs_apply_workspace(int32_t n_x, int32_t m);
+int otm_pairs_apply(const otm_csr* G1T, const otm_csr* G2, const double* V, int32_t m, double* out, void* ws,
+                    size_t ws_bytes, otm_stream stream);
+
+/* Rank-k randomized pseudo-inverse of P (n1 x n2) in factored form, from its
+ * sketches J = P S_right (n1 x m) and K = P^T S_left (n2 x m), both FP64
+ * row-major, and S_left (n1 x m).  The algorithm "Randomized Pseudoinverse"
+ * of Section 4.2 is printed for a symmetric P and one sketch; it is taken here
+ * from both sides (it reduces to the printed form when P is symmetric and
+ * S_left = S_right):
+ *   Psi = S_left^T J, its top-k singular triplets (U_k, s, V_k) from the
+ *   eigenpairs of Psi^T Psi; J V_k = Q_J R_J and K U_k = Q_K R_K (Cholesky QR
+ *   twice); core = R_K^-T diag(s) R_J^-1;  P^+ ~ Q_K core Q_J^T (n2 x n1).
+ * Outputs QJ (n1 x k), QK (n2 x k), core (k x k), sv (k singular values of
+ * Psi, descending; NULL allowed).  info: device int32, 0 on success, 1 when
+ * s_k <= 1e-12 s_1 or a QR pivot vanishes (results then undefined).
+ * 1 <= k <= m <= 256, k <= min(n1, n2, 200). */
+size_t otm_pinv_factors_workspace(int32_t n1, int32_t n2, int32_t m, int32_t k);
+int otm_pinv_factors(const double* J, const double* K, const double* S_left, int32_t n1, int32_t n2, int32_t m,
+                     int32_t k, double* QJ, double* QK, double* core, double* sv, int32_t* info, void* ws,
+                     size_t ws_bytes, otm_stream stream);
+
+/* Y (n_out x m) = Q_out M (Q_in^T X), M = core (trans == 0) or core^T
+ * (trans != 0): a low-rank factored product (Section 4.1).  Q_in: n_in x k,
+ * Q_out: n_out x k, core: k x k, X: n_in x m, all FP64 row-major. */
+size_t otm_factored_apply_workspace(int32_t n_in, int32_t k, int32_t m);
+int otm_factored_apply(const double* Q_in, int32_t n_in, const double* core, int trans, const double* Q_out,
+                       int32_t n_out, int32_t k, const double* X, int32_t m, double* Y, void* ws, size_t ws_bytes,
+                       otm_stream stream);
+
+/* Transposed transition products (Section 4.1: y_B = W^T Z_B G[x, B]^T,
+ * y_C = W^T Z_C G[x, C]^T) with Z_B = Pairs(A, C) Pairs(B, C)^+ and
+ * Z_C = Pairs(A, B) Pairs(C, B)^+, Pairs(B, C)^+ ~ QK core QJ^T from
+ * otm_pinv_factors(J = Pairs(B, C) S_C, K = Pairs(C, B) S_B, S_left = S_B):
+ *   view 1: out (n_B x m) = Z_B^T V = QJ core^T QK^T Pairs(C, A) V
+ *   view 2: out (n_C x m) = Z_C^T V = QK core QJ^T Pairs(B, A) V
+ * V: n_A x m FP64 (for W_B = Z_B^T W, W_C = Z_C^T W: V = W, m = k). */
+size_t otm_transition_t_workspace(const otm_partition* G, int32_t k, int32_t m);
+int otm_transition_t_apply(const otm_partition* G, const double* QJ, const double* QK, const double* core, int32_t k,
+                           int view, const double* V, int32_t m, double* out, void* ws, size_t ws_bytes,
+                           otm_stream stream);
+
+/* O (n_A x m) = M2 S for the second moment of Eq. 2moment_graph, without
+ * forming it:  M2 = (alpha0+1)/n_X sum_x Z_C G[x, C]^T G[x, B] Z_B^T
+ * - alpha0 M1 M1^T,  M1 = (1/n_X) sum_x G[x, A]^T, applied right to left:
+ * (alpha0+1) Z_C Pairs(C, B) (Z_B^T S) - alpha0 M1 (M1^T S).  S: n_A x m FP64. */
+size_t otm_m2_apply_four_workspace(const otm_partition* G, int32_t k, int32_t m);
+int otm_m2_apply_four(const otm_partition* G, const double* QJ, const double* QK, const double* core, int32_t k,
+                      double alpha0, const double* S, int32_t m, double* O, void* ws, size_t ws_bytes,
+                      otm_stream stream);
+
+/* FP64 rows X (rows x cols, row stride ldx) to out (rows x ldo) in OTM_F32 or
+ * OTM_BF16 (round to nearest even), columns cols..ldo-1 written with 0: the
+ * low-precision copy the whitening SpMM gathers (W_B, W_C). */
+int otm_cast_rows(const double* X, int32_t rows, int32_t cols, int32_t ldx, void* out, int dtype, int32_t ldo,
+                  otm_stream stream);
 
 /* ---- a3: whitening SpMM (Section 3.1 whitened data; Appendix A) ----------
  * Y[t, :] = r_t * sum_j C[t, j] W[j, :],  r_t = 1 / (row sum) if normalize
@@ -388,6 +479,34 @@ size_t otm_recover_pi_workspace(int32_t k);
 int otm_recover_pi(const void* Y, int y_dtype, int32_t ldy, int32_t n, int32_t k,
                    const float* Phi, double theta, double tau, float* Pi,
                    void* ws, size_t ws_bytes, otm_stream stream);
+
+/* ---- validation against ground truth (Section 5.1, p-value testing;
+ * Section 5.2, evaluation metrics) ------------------------------------------
+ * Pi_hat: k_hat x n estimated memberships (rows = communities, FP32), Pi:
+ * k x n true memberships of the same n nodes (FP32).  FP64 arithmetic:
+ *   rho (k_hat x k): Pearson correlation of row i of Pi_hat with row j of Pi
+ *     (0 when either row is constant);
+ *   pval: right p-value P(t_(n-2) > T), T = rho sqrt(n-2) / sqrt(1-rho^2)
+ *     (READING: the printed 1 - P(t > T) contradicts the stated right tail);
+ *   padj: Benjamini-Hochberg adjusted p-values over all k_hat * k tests
+ *     (READING of the false-discovery-rate adjustment), ties by position;
+ *   edges (int32 0/1): padj <= threshold (the paper uses 0.01);
+ *   l1: (1/n) sum_x |Pi_hat_i(x) - Pi_j(x)|;
+ *   scores[0] = recovery ratio R = (1/k) #{j with an edge},
+ *   scores[1] = error E = (1/k) sum over the edges of l1.
+ * k_hat * k <= 16384, n >= 3.  Fixed-order sums; deterministic. */
+size_t otm_validate_workspace(int32_t k_hat, int32_t k, int32_t n);
+int otm_validate(const float* Pi_hat, int32_t k_hat, const float* Pi, int32_t k, int32_t n, double threshold,
+                 double* rho, double* pval, double* padj, int32_t* edges, double* l1, double* scores, void* ws,
+                 size_t ws_bytes, otm_stream stream);
+
+/* Bridgeness of every node (Eq. bridgeness):
+ * b_x = 1 - sqrt(k_hat/(k_hat-1) sum_j (Pi_hat_j(x) - 1/k_hat)^2), k_hat >= 2;
+ * with the graph G (one row per node, NULL allowed) also the degree-corrected
+ * b_degree_x = D_x b_x (Eq. degreebridgeness), D_x the row's sum of values
+ * (its degree).  b, b_degree: n FP64 (b_degree NULL allowed; needs G). */
+int otm_bridgeness(const float* Pi_hat, int32_t k_hat, int32_t n, const otm_csr* G, double* b, double* b_degree,
+                   otm_stream stream);
 
 /* ---- loss (measurement only; the hot path never forms the tensor) --------
  * T (k x k x k FP64, T[(a*k + b)*k + c]) = the whitened tensor of Section

@@ -16,7 +16,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "NotPSDError", "as_sparse", "row_weights", "dirichlet_coefficients", "first_moment",
-    "m2_apply", "power_sketch", "whitener_rsvd", "canonical_signs", "whiten", "sgd_step", "sgd_direction",
+    "m2_apply", "power_sketch", "power_sketch_op", "whitener_rsvd", "canonical_signs", "whiten", "sgd_step", "sgd_direction",
     "sgd_run", "beta_schedule", "steps_per_pass", "whitened_tensor", "residual",
     "unwhiten_topics", "recover_pi", "eigen_from_factors", "restart_score", "best_restart", "sgd_batched",
 ]
@@ -105,10 +105,16 @@ def power_sketch(C, S: np.ndarray, alpha0: float, normalize: bool, q: int):
     method sketch of the Nystrom analysis the paper cites; q = 0 is the
     paper's algorithm.  Returns (Q_q, O = M2 Q_q) for whitener_rsvd(O, Q_q, k).
     """
+    return power_sketch_op(lambda V: m2_apply(C, V, alpha0, normalize), S, q)
+
+
+def power_sketch_op(apply_m2, S: np.ndarray, q: int):
+    """The power iteration of power_sketch for any second-moment operator
+    apply_m2(V) = M2 V: Q_0 = S, Q_j = orth(M2 Q_{j-1}); returns (Q_q, M2 Q_q)."""
     Q = S
     for _ in range(q):
-        Q = np.linalg.qr(m2_apply(C, Q, alpha0, normalize))[0]
-    return Q, m2_apply(C, Q, alpha0, normalize)
+        Q = np.linalg.qr(apply_m2(Q))[0]
+    return Q, apply_m2(Q)
 
 
 def canonical_signs(W: np.ndarray) -> np.ndarray:

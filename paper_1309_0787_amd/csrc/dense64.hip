@@ -441,6 +441,48 @@ __global__ void col_normalize_kernel(double* __restrict__ mu, const double* __re
 constexpr int kColBlocks = 128;
 
 }  // namespace
+
+// ------------------------------------------- shared with other translation units
+size_t gemm_tn_f64_ws(int d, int p, int q) { return gemm_tn_ws(d, p, q); }
+int gemm_tn_f64(const double* A, int lda, const double* B, int ldb, int d, int p, int q, double* C, double* part,
+                hipStream_t s) {
+    return gemm_tn(A, lda, B, ldb, d, p, q, C, part, s);
+}
+int gemm_nn_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int d, int p, int q,
+                hipStream_t s) {
+    return gemm_nn(A, lda, B, ldb, C, ldc, d, p, q, s);
+}
+
+size_t cholqr2_ws(int d, int m) {
+    size_t b = ws_round(sizeof(double) * (size_t)m * m) * 3;   // Gram, R1inv, R2inv
+    b += gemm_tn_ws(d, m, m);
+    b += ws_round(sizeof(double) * (size_t)d * m);             // first pass
+    return b;
+}
+
+int cholqr2(const double* Y, int d, int m, double* Q, double* Rinv, int32_t* info, void* ws, hipStream_t s) {
+    if (m > kCholN) return fail(OTM_ECAPACITY, "Cholesky QR needs m <= 200");
+    WsCarver wc(ws, cholqr2_ws(d, m));
+    double* Gr = wc.take<double>((size_t)m * m);
+    double* R1 = wc.take<double>((size_t)m * m);
+    double* R2 = wc.take<double>((size_t)m * m);
+    double* part = wc.take<double>(gemm_tn_ws(d, m, m) / sizeof(double));
+    double* Q1 = wc.take<double>((size_t)d * m);
+    int st;
+    const double* src = Y;
+    for (int pass = 0; pass < 2; ++pass) {
+        double* dst = pass == 0 ? Q1 : Q;
+        double* Ri = pass == 0 ? R1 : R2;
+        if ((st = gemm_tn(src, m, src, m, d, m, m, Gr, part, s)) != OTM_OK) return st;
+        hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), 0, s, Gr, m, Ri, info, pass);
+        if ((st = check_launch("chol_rinv_kernel")) != OTM_OK) return st;
+        if ((st = gemm_nn(src, m, Ri, m, dst, m, d, m, m, s)) != OTM_OK) return st;
+        src = Q1;
+    }
+    // Y = Q R2 R1, so R^-1 = R1^-1 R2^-1
+    return gemm_nn(R1, m, R2, m, Rinv, m, m, m, m, s);
+}
+
 }  // namespace otm
 
 using namespace otm;

@@ -49,6 +49,24 @@ int validate_csr_header(const otm_csr* C, const char* name);
 size_t jacobi_ws_bytes(int n);
 int jacobi(double* A, double* V, int n, double* evals, int* order, void* ws, hipStream_t s);
 
+// FP64 dense products (dense64.hip): C (p x q) = A^T B for tall A (d x p),
+// B (d x q), split over row chunks into `part` (gemm_tn_f64_ws bytes), then a
+// fixed-order reduction; C (d x q) = A B for tall A (d x p), small B (p x q).
+size_t gemm_tn_f64_ws(int d, int p, int q);
+int gemm_tn_f64(const double* A, int lda, const double* B, int ldb, int d, int p, int q, double* C, double* part,
+                hipStream_t s);
+int gemm_nn_f64(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int d, int p, int q,
+                hipStream_t s);
+// Cholesky QR applied twice (m <= 200): Q (d x m) orthonormal with Y = Q R,
+// and Rinv = R^-1 (m x m, upper triangular).  info as in otm_orthonormalize.
+size_t cholqr2_ws(int d, int m);
+int cholqr2(const double* Y, int d, int m, double* Q, double* Rinv, int32_t* info, void* ws, hipStream_t s);
+
+// FP64 sparse-dense product (spmm.hip): Y[r, :] = scale sum_j C[r, j] X[j, :]
+// for m <= 256 columns, rows of X and Y m apart.  Out-of-range columns are
+// skipped as in every kernel of the library.
+int spmm64(const otm_csr& C, const double* X, int m, double scale, double* Y, hipStream_t s);
+
 // ------------------------------------------------------------- numerics
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

@@ -571,7 +571,211 @@ __global__ void m2_epilogue_kernel(double* __restrict__ O, const double* __restr
     O[idx] = scale * (O[idx] - u[a] * S[idx]) - alpha0 * M1[a] * v[c];
 }
 
+// out[i] = v for i < n (a kernel, not a memset node, so the call can be captured)
+__global__ void fill_f32_kernel(float* __restrict__ out, int n, float v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+__global__ void set_i32_kernel(int32_t* __restrict__ out, int32_t v) { *out = v; }
+
+// ---------------------------------------------------------------------------
+// M2 applied to a column selection with random signs (Section 4.2, sparse
+// M2): O[:, j] = s_j M2[:, r_j]
+//   = s_j [(alpha0+1)/n (sum_t w2_t c_t[r_j] c_t - u[r_j] e_(r_j)) - alpha0 M1 M1[r_j]],
+// u = C^T w2, M1 = (1/n) C^T w1.  A column of M2 needs only the samples t
+// with c_t[r_j] != 0 (row r_j of C^T) and their rows.
+// ---------------------------------------------------------------------------
+// w1, w2 of every row (one wave per row); info = 1 for a document under 2 tokens
+__global__ __launch_bounds__(kM2Threads) void row_weights_kernel(otm_csr C, int normalize, double* __restrict__ w1,
+                                                                 double* __restrict__ w2, int32_t* info) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kM2Threads + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * kM2Threads) >> 6;
+    for (int row = wave; row < C.n_rows; row += nwaves) {
+        int64_t b, e;
+        clamp_row(C.rowptr, C.nnz, row, b, e);
+        double rs = 0.0;
+        for (int64_t p = b + lane; p < e; p += 64) {
+            const int32_t c = C.colidx[p];
+            if (c >= 0 && c < C.n_cols) rs += C.vals ? static_cast<double>(C.vals[p]) : 1.0;
+        }
+        for (int o = 32; o > 0; o >>= 1) rs += __shfl_xor(rs, o);
+        if (lane == 0) {
+            double a1 = 1.0, a2 = 1.0;
+            if (normalize) {
+                if (rs < 2.0) {
+                    *info = 1;
+                    a1 = a2 = 0.0;
+                } else {
+                    a1 = 1.0 / rs;
+                    a2 = 1.0 / (rs * (rs - 1.0));
+                }
+            }
+            w1[row] = a1;
+            w2[row] = a2;
+        }
+    }
+}
+
+// u[a] = sum_x CT[a, x] w2[x], M1[a] = inv_n sum_x CT[a, x] w1[x] (one wave per row of CT)
+__global__ __launch_bounds__(kM2Threads) void col_weights_kernel(otm_csr CT, const double* __restrict__ w1,
+                                                                 const double* __restrict__ w2, double inv_n,
+                                                                 double* __restrict__ u, double* __restrict__ M1) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kM2Threads + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * kM2Threads) >> 6;
+    for (int row = wave; row < CT.n_rows; row += nwaves) {
+        int64_t b, e;
+        clamp_row(CT.rowptr, CT.nnz, row, b, e);
+        double su = 0.0, sm = 0.0;
+        for (int64_t p = b + lane; p < e; p += 64) {
+            const int32_t x = CT.colidx[p];
+            if (x < 0 || x >= CT.n_cols) continue;
+            const double v = CT.vals ? static_cast<double>(CT.vals[p]) : 1.0;
+            su += v * w2[x];
+            sm += v * w1[x];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            su += __shfl_xor(su, o);
+            sm += __shfl_xor(sm, o);
+        }
+        if (lane == 0) {
+            u[row] = su;
+            M1[row] = sm * inv_n;
+        }
+    }
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ out, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+// One workgroup per selected column j: O[:, j] += scale w2_t c_t[r_j] s_j c_t
+// over the samples t of row r_j of C^T, in their stored order; the entries of
+// one sample's row are distinct columns, so its threads never collide, and a
+// barrier separates consecutive samples.  info = 2 for a row outside [0, d).
+__global__ __launch_bounds__(kM2Threads) void select_scatter_kernel(otm_csr C, otm_csr CT,
+                                                                    const int32_t* __restrict__ sel,
+                                                                    const double* __restrict__ sgn,
+                                                                    const double* __restrict__ w2, double scale, int kt,
+                                                                    double* __restrict__ O, int32_t* info) {
+    const int j = blockIdx.x;
+    const int r = sel[j];
+    if (r < 0 || r >= CT.n_rows) {
+        if (threadIdx.x == 0) *info = 2;
+        return;
+    }
+    const double sj = sgn[j];
+    int64_t b, e;
+    clamp_row(CT.rowptr, CT.nnz, r, b, e);
+    for (int64_t p = b; p < e; ++p) {
+        const int32_t t = CT.colidx[p];
+        if (t < 0 || t >= C.n_rows) continue;
+        const double coef = scale * w2[t] * (CT.vals ? static_cast<double>(CT.vals[p]) : 1.0) * sj;
+        int64_t tb, te;
+        clamp_row(C.rowptr, C.nnz, t, tb, te);
+        for (int64_t q = tb + threadIdx.x; q < te; q += kM2Threads) {
+            const int32_t a = C.colidx[q];
+            if (a < 0 || a >= C.n_cols) continue;
+            O[(size_t)a * kt + j] += coef * (C.vals ? static_cast<double>(C.vals[q]) : 1.0);
+        }
+        __syncthreads();
+    }
+}
+
+// O[a, j] -= alpha0 M1[a] M1[r_j] s_j, and at a = r_j also scale u[r_j] s_j
+__global__ void select_epilogue_kernel(double* __restrict__ O, const int32_t* __restrict__ sel,
+                                       const double* __restrict__ sgn, const double* __restrict__ u,
+                                       const double* __restrict__ M1, int d, int kt, double scale, double alpha0) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)d * kt) return;
+    const int a = static_cast<int>(idx / kt), j = static_cast<int>(idx % kt);
+    const int r = sel[j];
+    if (r < 0 || r >= d) return;
+    double v = O[idx] - alpha0 * M1[a] * M1[r] * sgn[j];
+    if (a == r) v -= scale * u[r] * sgn[j];
+    O[idx] = v;
+}
+
+__global__ void selection_dense_kernel(const int32_t* __restrict__ sel, const double* __restrict__ sgn, int d, int kt,
+                                       double* __restrict__ S) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)d * kt) return;
+    const int a = static_cast<int>(idx / kt), j = static_cast<int>(idx % kt);
+    S[idx] = (sel[j] == a) ? sgn[j] : 0.0;
+}
+
+// Y[row, :] = scale sum_j C[row, j] X[j, :]: the first M2 pass without its
+// weights (one wave per row, kM2Unroll entries loaded together, entries
+// summed in order).
+template <bool V2>
+__global__ __launch_bounds__(kM2Threads) void spmm64_kernel(otm_csr C, const double* __restrict__ X, int m,
+                                                            double scale, double* __restrict__ Y) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kM2Threads + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * kM2Threads) >> 6;
+    for (int row = wave; row < C.n_rows; row += nwaves) {
+        int64_t b, e;
+        clamp_row(C.rowptr, C.nnz, row, b, e);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int64_t p = b;
+        for (; p + kM2Unroll <= e; p += kM2Unroll) {
+            int32_t cc[kM2Unroll];
+            double vv[kM2Unroll], xv[kM2Unroll][4];
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                cc[x] = C.colidx[p + x];
+                vv[x] = C.vals ? static_cast<double>(C.vals[p + x]) : 1.0;
+            }
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                const bool ok = cc[x] >= 0 && cc[x] < C.n_cols;
+                m2_load<V2>(X + (size_t)(ok ? cc[x] : 0) * m, lane, m, ok, xv[x]);
+            }
+#pragma unroll
+            for (int x = 0; x < kM2Unroll; ++x) {
+                if (cc[x] < 0 || cc[x] >= C.n_cols) continue;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (m2_col<V2>(lane, u) < m) acc[u] += vv[x] * xv[x][u];
+            }
+        }
+        for (; p < e; ++p) {
+            const int32_t c = C.colidx[p];
+            if (c < 0 || c >= C.n_cols) continue;
+            const double v = C.vals ? static_cast<double>(C.vals[p]) : 1.0;
+            double xv[4];
+            m2_load<V2>(X + (size_t)c * m, lane, m, true, xv);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (m2_col<V2>(lane, u) < m) acc[u] += v * xv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int col = m2_col<V2>(lane, u);
+            if (col < m) Y[(size_t)row * m + col] = scale * acc[u];
+        }
+    }
+}
+
 }  // namespace
+
+int spmm64(const otm_csr& C, const double* X, int m, double scale, double* Y, hipStream_t s) {
+    if (m < 1 || m > 256) return fail(OTM_ECAPACITY, "FP64 SpMM needs 1 <= m <= 256 columns");
+    if (C.n_rows == 0) return OTM_OK;
+    const int waves_per_block = kM2Threads / 64;
+    int64_t nb = (C.n_rows + waves_per_block - 1) / waves_per_block;
+    const int blocks = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
+    const bool v2 = m % 2 == 0 && (reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16 == 0;
+    if (v2)
+        hipLaunchKernelGGL(spmm64_kernel<true>, dim3(blocks), dim3(kM2Threads), 0, s, C, X, m, scale, Y);
+    else
+        hipLaunchKernelGGL(spmm64_kernel<false>, dim3(blocks), dim3(kM2Threads), 0, s, C, X, m, scale, Y);
+    return check_launch("spmm64_kernel");
+}
+
 }  // namespace otm
 
 using namespace otm;
@@ -585,9 +789,12 @@ extern "C" size_t otm_whiten_workspace(int32_t n_rows, int32_t k) {
     return ws_round(sizeof(float) * (size_t)nb * k);
 }
 
-extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
-                          void* Y, int y_dtype, int32_t ldy, float* ybar, void* ws, size_t ws_bytes,
-                          otm_stream stream) {
+namespace otm {
+namespace {
+
+// The whitening call on a given partial-sum buffer of part_floats floats.
+int whiten_impl(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw, void* Y,
+                int y_dtype, int32_t ldy, float* ybar, float* part, size_t part_floats, hipStream_t s) {
     int st = validate_csr_header(C, "C");
     if (st != OTM_OK) return st;
     OTM_REQUIRE(W != nullptr && (Y != nullptr || C->n_rows == 0), OTM_EINVAL, "W and Y must not be NULL");
@@ -598,18 +805,16 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
     OTM_REQUIRE(y_dtype != OTM_F32 || ldy % 4 == 0, OTM_ESHAPE, "F32 Y needs ldy % 4 == 0");
     WhitenPlan p = plan_whiten(C->n_rows, k, ldw, w_dtype, reinterpret_cast<uintptr_t>(W));
     OTM_REQUIRE(p.lpr <= 64, OTM_ECAPACITY, "k too large for the whitening kernel (k <= 64 * vector width)");
-    OTM_REQUIRE(ws != nullptr && ws_bytes >= otm_whiten_workspace(C->n_rows, k), OTM_EWORKSPACE,
-                "whiten workspace too small");
     if (C->n_rows == 0) {
         if (ybar) {
-            hipError_t e = hipMemsetAsync(ybar, 0, sizeof(float) * k, as_stream(stream));
-            if (e != hipSuccess) return hip_fail(e, "whiten ybar clear");
+            hipLaunchKernelGGL(fill_f32_kernel, dim3((k + 255) / 256), dim3(256), 0, s, ybar, k, 0.0f);
+            return check_launch("fill_f32_kernel");
         }
         return OTM_OK;
     }
-    hipStream_t s = as_stream(stream);
-    float* part = static_cast<float*>(ws);
     plan_whiten_lds(p, *C, k, w_dtype);
+    OTM_REQUIRE(part != nullptr && (size_t)p.nblocks * k <= part_floats, OTM_EWORKSPACE,
+                "whitening partial sums need more space than given");
     if (p.lds) {
         if (w_dtype == OTM_F32)
             st = (y_dtype == OTM_F32)
@@ -635,6 +840,19 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
         return check_launch("colsum_finalize_kernel");
     }
     return OTM_OK;
+}
+
+}  // namespace
+}  // namespace otm
+
+extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
+                          void* Y, int y_dtype, int32_t ldy, float* ybar, void* ws, size_t ws_bytes,
+                          otm_stream stream) {
+    const int32_t rows = C ? C->n_rows : 0;
+    OTM_REQUIRE(C == nullptr || rows == 0 || (ws != nullptr && ws_bytes >= otm_whiten_workspace(rows, k)),
+                OTM_EWORKSPACE, "whiten workspace too small");
+    return whiten_impl(C, normalize, W, w_dtype, k, ldw, Y, y_dtype, ldy, ybar, static_cast<float*>(ws),
+                       ws_bytes / sizeof(float), as_stream(stream));
 }
 
 extern "C" size_t otm_m2_apply_workspace(int32_t n, int32_t d, int32_t k_tilde) {
@@ -672,8 +890,8 @@ extern "C" int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, 
     double* M1 = wc.take<double>(d);
     double* part = wc.take<double>((size_t)kWcsBlocks * k_tilde);
     double* v = wc.take<double>(k_tilde);
-    hipError_t e = hipMemsetAsync(info, 0, sizeof(int32_t), s);
-    if (e != hipSuccess) return hip_fail(e, "m2_apply info clear");
+    hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(1), 0, s, info, 0);
+    if ((st = check_launch("set_i32_kernel")) != OTM_OK) return st;
     const int waves_per_block = kM2Threads / 64;
     auto blocks_for = [&](int rows) {
         int64_t b = (rows + waves_per_block - 1) / waves_per_block;
@@ -704,4 +922,62 @@ extern "C" int otm_m2_apply(const otm_csr* C, const otm_csr* CT, int normalize, 
     hipLaunchKernelGGL(m2_epilogue_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, O, S, u, M1, v, d,
                        k_tilde, (alpha0 + 1.0) / n, alpha0);
     return check_launch("m2_epilogue_kernel");
+}
+
+extern "C" size_t otm_m2_apply_select_workspace(int32_t n, int32_t d) {
+    if (n < 0 || d < 0) return 0;
+    return 2 * ws_round(sizeof(double) * (size_t)n) + 2 * ws_round(sizeof(double) * (size_t)d);
+}
+
+extern "C" int otm_m2_apply_select(const otm_csr* C, const otm_csr* CT, int normalize, double alpha0,
+                                   const int32_t* sel_rows, const double* sel_signs, int32_t k_tilde, double* O,
+                                   int32_t* info, void* ws, size_t ws_bytes, otm_stream stream) {
+    int st = validate_csr_header(C, "C");
+    if (st != OTM_OK) return st;
+    if ((st = validate_csr_header(CT, "CT")) != OTM_OK) return st;
+    OTM_REQUIRE(sel_rows && sel_signs && O && info, OTM_EINVAL, "sel_rows, sel_signs, O, info must not be NULL");
+    OTM_REQUIRE(CT->n_rows == C->n_cols && CT->n_cols == C->n_rows && CT->nnz == C->nnz, OTM_ESHAPE,
+                "CT must be the transpose of C");
+    OTM_REQUIRE(k_tilde >= 1 && k_tilde <= 256, OTM_ECAPACITY, "need 1 <= k_tilde <= 256");
+    OTM_REQUIRE(C->n_rows >= 1, OTM_ESHAPE, "need at least one sample");
+    OTM_REQUIRE(std::isfinite(alpha0) && alpha0 >= 0.0, OTM_EINVAL, "alpha0 must be finite and >= 0");
+    const int n = C->n_rows, d = C->n_cols;
+    OTM_REQUIRE(ws && ws_bytes >= otm_m2_apply_select_workspace(n, d), OTM_EWORKSPACE,
+                "m2_apply_select workspace too small");
+    hipStream_t s = as_stream(stream);
+    WsCarver wc(ws, ws_bytes);
+    double* w1 = wc.take<double>(n);
+    double* w2 = wc.take<double>(n);
+    double* u = wc.take<double>(d);
+    double* M1 = wc.take<double>(d);
+    auto blocks_for = [&](int rows) {
+        int64_t b = (rows + kM2Threads / 64 - 1) / (kM2Threads / 64);
+        return static_cast<int>(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    };
+    const double scale = (alpha0 + 1.0) / n;
+    const int64_t total = (int64_t)d * k_tilde;
+    hipLaunchKernelGGL(set_i32_kernel, dim3(1), dim3(1), 0, s, info, 0);
+    if ((st = check_launch("set_i32_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(row_weights_kernel, dim3(blocks_for(n)), dim3(kM2Threads), 0, s, *C, normalize, w1, w2, info);
+    if ((st = check_launch("row_weights_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(col_weights_kernel, dim3(blocks_for(d)), dim3(kM2Threads), 0, s, *CT, w1, w2, 1.0 / n, u, M1);
+    if ((st = check_launch("col_weights_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, O, total, 0.0);
+    if ((st = check_launch("fill_f64_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(select_scatter_kernel, dim3(k_tilde), dim3(kM2Threads), 0, s, *C, *CT, sel_rows, sel_signs, w2,
+                       scale, k_tilde, O, info);
+    if ((st = check_launch("select_scatter_kernel")) != OTM_OK) return st;
+    hipLaunchKernelGGL(select_epilogue_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, O, sel_rows,
+                       sel_signs, u, M1, d, k_tilde, scale, alpha0);
+    return check_launch("select_epilogue_kernel");
+}
+
+extern "C" int otm_selection_dense(const int32_t* sel_rows, const double* sel_signs, int32_t d, int32_t k_tilde,
+                                   double* S, otm_stream stream) {
+    OTM_REQUIRE(sel_rows && sel_signs && S, OTM_EINVAL, "sel_rows, sel_signs, S must not be NULL");
+    OTM_REQUIRE(d >= 1 && k_tilde >= 1, OTM_ESHAPE, "need d, k_tilde >= 1");
+    const int64_t total = (int64_t)d * k_tilde;
+    hipLaunchKernelGGL(selection_dense_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, as_stream(stream),
+                       sel_rows, sel_signs, d, k_tilde, S);
+    return check_launch("selection_dense_kernel");
 }

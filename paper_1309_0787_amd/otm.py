@@ -46,6 +46,10 @@ class _CSR(ctypes.Structure):
                 ("rowptr", _vp), ("colidx", _vp), ("vals", _vp)]
 
 
+class _Partition(ctypes.Structure):
+    _fields_ = [("XA", _CSR), ("XB", _CSR), ("XC", _CSR), ("AX", _CSR), ("BX", _CSR), ("CX", _CSR)]
+
+
 class _SgdParams(ctypes.Structure):
     _fields_ = [("k", _i32), ("batch", _i32), ("passes", _i32), ("ldy", _i32), ("y_dtype", _i32),
                 ("compensated", _i32), ("alpha0", _dbl), ("theta", _dbl), ("beta0", _dbl),
@@ -69,11 +73,30 @@ _SIGS = {
     "otm_m2_apply_workspace": (_sz, [_i32, _i32, _i32]),
     "otm_m2_apply": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), ctypes.c_int, _dbl, _vp, _i32,
                                     _vp, _vp, _vp, _sz, _vp]),
+    "otm_m2_apply_select_workspace": (_sz, [_i32, _i32]),
+    "otm_m2_apply_select": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), ctypes.c_int, _dbl, _vp, _vp,
+                                           _i32, _vp, _vp, _vp, _sz, _vp]),
+    "otm_selection_dense": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp]),
     "otm_whitener_workspace": (_sz, [_i32, _i32, _i32]),
     "otm_whitener": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _i32, _vp, _vp, _sz,
                                     _vp]),
     "otm_orthonormalize_workspace": (_sz, [_i32, _i32]),
     "otm_orthonormalize": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "otm_pairs_apply_workspace": (_sz, [_i32, _i32]),
+    "otm_pairs_apply": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.POINTER(_CSR), _vp, _i32, _vp, _vp, _sz, _vp]),
+    "otm_pinv_factors_workspace": (_sz, [_i32, _i32, _i32, _i32]),
+    "otm_pinv_factors": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                        _vp]),
+    "otm_factored_apply_workspace": (_sz, [_i32, _i32, _i32]),
+    "otm_factored_apply": (ctypes.c_int, [_vp, _i32, _vp, ctypes.c_int, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz,
+                                          _vp]),
+    "otm_transition_t_workspace": (_sz, [ctypes.POINTER(_Partition), _i32, _i32]),
+    "otm_transition_t_apply": (ctypes.c_int, [ctypes.POINTER(_Partition), _vp, _vp, _vp, _i32, ctypes.c_int, _vp,
+                                              _i32, _vp, _vp, _sz, _vp]),
+    "otm_m2_apply_four_workspace": (_sz, [ctypes.POINTER(_Partition), _i32, _i32]),
+    "otm_m2_apply_four": (ctypes.c_int, [ctypes.POINTER(_Partition), _vp, _vp, _vp, _i32, _dbl, _vp, _i32, _vp, _vp,
+                                         _sz, _vp]),
+    "otm_cast_rows": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.c_int, _i32, _vp]),
     "otm_whiten_workspace": (_sz, [_i32, _i32]),
     "otm_whiten": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _i32, _vp,
                                   ctypes.c_int, _i32, _vp, _vp, _sz, _vp]),
@@ -117,6 +140,9 @@ _SIGS = {
     "otm_unwhiten_topics": (ctypes.c_int, [_vp, _i32, _i32, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "otm_recover_pi_workspace": (_sz, [_i32]),
     "otm_recover_pi": (ctypes.c_int, [_vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _dbl, _vp, _vp, _sz, _vp]),
+    "otm_validate_workspace": (_sz, [_i32, _i32, _i32]),
+    "otm_validate": (ctypes.c_int, [_vp, _i32, _vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "otm_bridgeness": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_CSR), _vp, _vp, _vp]),
     "otm_tensor_form": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _vp, _vp]),
     "otm_residual_workspace": (_sz, [_i32, _i32]),
     "otm_residual": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
@@ -134,7 +160,11 @@ def lib() -> ctypes.CDLL:
                                "(paper_1309_0787_amd.build.build())")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
-            f = getattr(L, name)
+            # a library older than this binding lacks some entry points:
+            # only calls of those fail (the ABI test checks every export)
+            f = getattr(L, name, None)
+            if f is None:
+                continue
             f.restype = res
             f.argtypes = args
         _lib = L
@@ -210,18 +240,80 @@ def csr_check(C: DeviceCSR, stream=None) -> int:
 
 
 # ------------------------------------------------------------------ a1, a2
-def m2_apply(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: torch.Tensor, stream=None):
-    """O = M2 S (FP64).  Raises OtmError if a document has fewer than 2 tokens."""
+def _info_slot(info, device):
+    """(slot, deferred): a caller's 1-element int32 device tensor receives the
+    entry point's device status and is checked later (check_info); without one
+    a fresh slot is checked right after the call (a stream synchronisation)."""
+    if info is None:
+        return torch.zeros(1, dtype=torch.int32, device=device), False
+    if info.dtype != torch.int32 or info.numel() != 1 or not info.is_cuda:
+        raise OtmError(-1, "info must be a 1-element int32 GPU tensor")
+    return info, True
+
+
+_INFO_ERRORS = {
+    "pinv_factors": (OtmNotPSD, -4, "sketched pairs matrix has no rank-k part (s_k <= 1e-12 s_1)"),
+    "m2_apply": (OtmError, -1, "a document has fewer than 2 tokens"),
+    "m2_apply_select": (OtmError, -1, "a document has fewer than 2 tokens or a selected row is out of range"),
+    "whitener": (OtmNotPSD, -4, "projected second moment has no k positive eigenvalues"),
+    "orthonormalize": (OtmError, -4, "sketch is rank deficient"),
+    "unwhiten_topics": (OtmError, -4, "W^T W is not positive definite"),
+}
+
+
+def _raise_info(kind: str):
+    cls, code, msg = _INFO_ERRORS[kind]
+    raise cls(code, msg)
+
+
+def check_info(infos: torch.Tensor, kinds: list[str]):
+    """Raises for the first non-zero device status among infos[i] (written by
+    the entry point kinds[i]); one synchronisation for all of them."""
+    codes = infos.cpu().tolist()
+    for c, kind in zip(codes, kinds):
+        if c != 0:
+            _raise_info(kind)
+
+
+def m2_apply(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: torch.Tensor, stream=None,
+             info: torch.Tensor | None = None):
+    """O = M2 S (FP64).  Raises OtmError if a document has fewer than 2 tokens
+    (at once, or through check_info when the caller passes an info slot)."""
     d, kt = S.shape
     O = torch.empty((d, kt), dtype=torch.float64, device=S.device)
-    info = torch.zeros(1, dtype=torch.int32, device=S.device)
+    info, deferred = _info_slot(info, S.device)
     ws = _ws(lib().otm_m2_apply_workspace(C.n_rows, C.n_cols, kt), S.device)
     c1, c2 = C.c(), CT.c()
     _check(lib().otm_m2_apply(ctypes.byref(c1), ctypes.byref(c2), int(normalize), float(alpha0), _ptr(S), kt,
                               _ptr(O), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
-    if int(info.item()) != 0:
-        raise OtmError(-1, "a document has fewer than 2 tokens")
+    if not deferred and int(info.item()) != 0:
+        _raise_info("m2_apply")
     return O
+
+
+def m2_apply_select(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, sel_rows: torch.Tensor,
+                    sel_signs: torch.Tensor, stream=None, info: torch.Tensor | None = None):
+    """O = M2 S for the column selection S[sel_rows[j], j] = sel_signs[j] (FP64)."""
+    if sel_rows.dtype != torch.int32 or sel_signs.dtype != torch.float64 or sel_rows.numel() != sel_signs.numel():
+        raise OtmError(-3, "sel_rows must be int32 and sel_signs FP64 of the same length")
+    kt = sel_rows.numel()
+    d = C.n_cols
+    O = torch.empty((d, kt), dtype=torch.float64, device=sel_rows.device)
+    info, deferred = _info_slot(info, sel_rows.device)
+    ws = _ws(lib().otm_m2_apply_select_workspace(C.n_rows, d), sel_rows.device)
+    c1, c2 = C.c(), CT.c()
+    _check(lib().otm_m2_apply_select(ctypes.byref(c1), ctypes.byref(c2), int(normalize), float(alpha0), _ptr(sel_rows),
+                                     _ptr(sel_signs), kt, _ptr(O), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
+    if not deferred and int(info.item()) != 0:
+        _raise_info("m2_apply_select")
+    return O
+
+
+def selection_dense(sel_rows: torch.Tensor, sel_signs: torch.Tensor, d: int, stream=None) -> torch.Tensor:
+    kt = sel_rows.numel()
+    S = torch.empty((d, kt), dtype=torch.float64, device=sel_rows.device)
+    _check(lib().otm_selection_dense(_ptr(sel_rows), _ptr(sel_signs), d, kt, _ptr(S), _stream(stream)))
+    return S
 
 
 def default_ldw(k: int, dtype: int) -> int:
@@ -231,7 +323,7 @@ def default_ldw(k: int, dtype: int) -> int:
 
 
 def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = F32, ldw_lo: int | None = None,
-             stream=None):
+             stream=None, info: torch.Tensor | None = None):
     """(W FP64 d x k, evals FP64 k, W_lo in w_lo_dtype or None).  W_lo is the
     d x k view of a d x ldw_lo buffer (default: k rounded up to 16 bytes) whose
     padding columns hold 0.  Raises OtmNotPSD."""
@@ -242,36 +334,174 @@ def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = 
     if w_lo_dtype is not None:
         ld = default_ldw(k, w_lo_dtype) if ldw_lo is None else int(ldw_lo)
         W_lo = torch.empty((d, ld), dtype=_TORCH_DTYPE[w_lo_dtype], device=O.device)
-    info = torch.zeros(1, dtype=torch.int32, device=O.device)
+    info, deferred = _info_slot(info, O.device)
     ws = _ws(lib().otm_whitener_workspace(d, kt, k), O.device)
     _check(lib().otm_whitener(_ptr(O), _ptr(S), d, kt, k, _ptr(W), _ptr(ev), _ptr(W_lo),
                               F32 if w_lo_dtype is None else w_lo_dtype, ld, _ptr(info), _ptr(ws), ws.numel(),
                               _stream(stream)))
-    if int(info.item()) != 0:
-        raise OtmNotPSD(-4, "projected second moment has no k positive eigenvalues")
+    if not deferred and int(info.item()) != 0:
+        _raise_info("whitener")
     return W, ev, (None if W_lo is None else W_lo[:, :k])
 
 
-def orthonormalize(Y: torch.Tensor, stream=None) -> torch.Tensor:
+def orthonormalize(Y: torch.Tensor, stream=None, info: torch.Tensor | None = None) -> torch.Tensor:
     """Q = Y (Y^T Y)^(-1/2) (FP64)."""
     d, m = Y.shape
     Q = torch.empty_like(Y)
-    info = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    info, deferred = _info_slot(info, Y.device)
     ws = _ws(lib().otm_orthonormalize_workspace(d, m), Y.device)
     _check(lib().otm_orthonormalize(_ptr(Y), d, m, _ptr(Q), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
-    if int(info.item()) != 0:
-        raise OtmError(-4, "sketch is rank deficient")
+    if not deferred and int(info.item()) != 0:
+        _raise_info("orthonormalize")
     return Q
 
 
 def power_sketch(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: torch.Tensor, q: int,
-                 stream=None):
+                 stream=None, infos: torch.Tensor | None = None):
     """Sketch for the whitener: Q_0 = S, Q_j = orth(M2 Q_{j-1}); returns
-    (Q_q, O = M2 Q_q).  q = 0 returns (S, M2 S)."""
+    (Q_q, O = M2 Q_q).  q = 0 returns (S, M2 S).  infos: None (each status
+    checked at once) or 2q + 1 int32 device slots, in call order
+    m2_apply, orthonormalize, ..., m2_apply (power_sketch_kinds(q))."""
+    if infos is not None and infos.numel() < 2 * q + 1:
+        raise OtmError(-1, f"power_sketch needs {2 * q + 1} info slots")
+    slot = (lambda i: None) if infos is None else (lambda i: infos[i:i + 1])
     Q = S
-    for _ in range(q):
-        Q = orthonormalize(m2_apply(C, CT, normalize, alpha0, Q, stream), stream)
-    return Q, m2_apply(C, CT, normalize, alpha0, Q, stream)
+    for j in range(q):
+        Q = orthonormalize(m2_apply(C, CT, normalize, alpha0, Q, stream, info=slot(2 * j)), stream,
+                           info=slot(2 * j + 1))
+    return Q, m2_apply(C, CT, normalize, alpha0, Q, stream, info=slot(2 * q))
+
+
+def power_sketch_kinds(q: int) -> list[str]:
+    return ["m2_apply", "orthonormalize"] * q + ["m2_apply"]
+
+
+# ------------------------------------------------------------------ four-partition graph moments
+class DevicePartition:
+    """The blocks G[X, A], G[X, B], G[X, C] of a graph and their transposes,
+    as DeviceCSRs (Section 2.2 node partition)."""
+
+    def __init__(self, XA, XB, XC, AX, BX, CX):
+        self.XA, self.XB, self.XC, self.AX, self.BX, self.CX = XA, XB, XC, AX, BX, CX
+
+    @staticmethod
+    def from_blocks(blocks: dict, device) -> "DevicePartition":
+        names = (("X", "A"), ("X", "B"), ("X", "C"), ("A", "X"), ("B", "X"), ("C", "X"))
+        return DevicePartition(*[DeviceCSR.from_host(blocks[n], device) for n in names])
+
+    def c(self) -> _Partition:
+        return _Partition(self.XA.c(), self.XB.c(), self.XC.c(), self.AX.c(), self.BX.c(), self.CX.c())
+
+    @property
+    def n_x(self):
+        return self.XA.n_rows
+
+    @property
+    def sizes(self):
+        return self.XA.n_cols, self.XB.n_cols, self.XC.n_cols
+
+    @property
+    def device(self):
+        return self.XA.device
+
+
+def pairs_apply(G1T: DeviceCSR, G2: DeviceCSR, V: torch.Tensor, stream=None) -> torch.Tensor:
+    """Pairs(Y1, Y2) V = (1/n_X) G[Y1, X] (G[X, Y2] V) (FP64)."""
+    n2, m = V.shape
+    out = torch.empty((G1T.n_rows, m), dtype=torch.float64, device=V.device)
+    ws = _ws(lib().otm_pairs_apply_workspace(G2.n_rows, m), V.device)
+    a, b = G1T.c(), G2.c()
+    _check(lib().otm_pairs_apply(ctypes.byref(a), ctypes.byref(b), _ptr(V), m, _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream(stream)))
+    return out
+
+
+@dataclass
+class PinvFactors:
+    """P^+ ~ QK core QJ^T (n2 x n1); sv: the top k singular values of Psi."""
+    QJ: torch.Tensor
+    QK: torch.Tensor
+    core: torch.Tensor
+    sv: torch.Tensor
+    k: int
+
+
+def pinv_factors(J: torch.Tensor, K: torch.Tensor, S_left: torch.Tensor, k: int, stream=None,
+                 info: torch.Tensor | None = None) -> PinvFactors:
+    """Rank-k randomized pseudo-inverse of P from J = P S_right, K = P^T S_left."""
+    n1, m = J.shape
+    n2 = K.shape[0]
+    dev = J.device
+    QJ = torch.empty((n1, k), dtype=torch.float64, device=dev)
+    QK = torch.empty((n2, k), dtype=torch.float64, device=dev)
+    core = torch.empty((k, k), dtype=torch.float64, device=dev)
+    sv = torch.empty(k, dtype=torch.float64, device=dev)
+    info, deferred = _info_slot(info, dev)
+    ws = _ws(lib().otm_pinv_factors_workspace(n1, n2, m, k), dev)
+    _check(lib().otm_pinv_factors(_ptr(J), _ptr(K), _ptr(S_left), n1, n2, m, k, _ptr(QJ), _ptr(QK), _ptr(core),
+                                  _ptr(sv), _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
+    if not deferred and int(info.item()) != 0:
+        _raise_info("pinv_factors")
+    return PinvFactors(QJ, QK, core, sv, k)
+
+
+def factored_apply(Q_in: torch.Tensor, core: torch.Tensor, trans: bool, Q_out: torch.Tensor, X: torch.Tensor,
+                   stream=None) -> torch.Tensor:
+    """Q_out M (Q_in^T X), M = core or core^T."""
+    n_in, k = Q_in.shape
+    n_out = Q_out.shape[0]
+    m = X.shape[1]
+    Y = torch.empty((n_out, m), dtype=torch.float64, device=X.device)
+    ws = _ws(lib().otm_factored_apply_workspace(n_in, k, m), X.device)
+    _check(lib().otm_factored_apply(_ptr(Q_in), n_in, _ptr(core), int(bool(trans)), _ptr(Q_out), n_out, k, _ptr(X), m,
+                                    _ptr(Y), _ptr(ws), ws.numel(), _stream(stream)))
+    return Y
+
+
+def transition_t_apply(G: DevicePartition, F: PinvFactors, view: int, V: torch.Tensor, stream=None) -> torch.Tensor:
+    """view 1: Z_B^T V (n_B x m); view 2: Z_C^T V (n_C x m)."""
+    m = V.shape[1]
+    rows = G.XB.n_cols if view == 1 else G.XC.n_cols
+    out = torch.empty((rows, m), dtype=torch.float64, device=V.device)
+    gc = G.c()
+    ws = _ws(lib().otm_transition_t_workspace(ctypes.byref(gc), F.k, m), V.device)
+    _check(lib().otm_transition_t_apply(ctypes.byref(gc), _ptr(F.QJ), _ptr(F.QK), _ptr(F.core), F.k, int(view), _ptr(V),
+                                        m, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def m2_apply_four(G: DevicePartition, F: PinvFactors, alpha0: float, S: torch.Tensor, stream=None) -> torch.Tensor:
+    """O = M2 S for the four-partition second moment (FP64)."""
+    m = S.shape[1]
+    O = torch.empty((G.XA.n_cols, m), dtype=torch.float64, device=S.device)
+    gc = G.c()
+    ws = _ws(lib().otm_m2_apply_four_workspace(ctypes.byref(gc), F.k, m), S.device)
+    _check(lib().otm_m2_apply_four(ctypes.byref(gc), _ptr(F.QJ), _ptr(F.QK), _ptr(F.core), F.k, float(alpha0), _ptr(S),
+                                   m, _ptr(O), _ptr(ws), ws.numel(), _stream(stream)))
+    return O
+
+
+def power_sketch_four(G: DevicePartition, F: PinvFactors, alpha0: float, S: torch.Tensor, q: int, stream=None,
+                      infos: torch.Tensor | None = None):
+    """The power-iterated sketch with the four-partition M2; infos: None or q
+    int32 device slots (the orthonormalisations)."""
+    if infos is not None and infos.numel() < q:
+        raise OtmError(-1, f"power_sketch_four needs {q} info slots")
+    Q = S
+    for j in range(q):
+        Q = orthonormalize(m2_apply_four(G, F, alpha0, Q, stream), stream,
+                           info=None if infos is None else infos[j:j + 1])
+    return Q, m2_apply_four(G, F, alpha0, Q, stream)
+
+
+def cast_rows(X: torch.Tensor, dtype: int, ld: int | None = None, stream=None) -> torch.Tensor:
+    """FP64 rows to an F32/BF16 copy with row stride ld (default: 16-byte rows);
+    returns the rows x cols view of the padded buffer."""
+    rows, cols = X.shape
+    ld = default_ldw(cols, dtype) if ld is None else int(ld)
+    out = torch.empty((rows, ld), dtype=_TORCH_DTYPE[dtype], device=X.device)
+    _check(lib().otm_cast_rows(_ptr(X), rows, cols, X.stride(0), _ptr(out), dtype, ld, _stream(stream)))
+    return out[:, :cols]
 
 
 # ------------------------------------------------------------------ a3
@@ -330,12 +560,31 @@ def sgd_step(p: SgdParams, rows: int, YA, YB, YC, ybar3: torch.Tensor, beta: flo
     return Phi
 
 
+def check_perms(perms: torch.Tensor | None, n: int, passes: int, restarts: int, perm_stride: int):
+    """The kernels read perms[r*perm_stride + p*n + i] for every run r, pass p
+    and row i (they range-check the values, not the buffer): refuse a buffer
+    of another type or too short for that."""
+    if perms is None:
+        return
+    if perms.dtype != torch.int32:
+        raise OtmError(-3, f"perms must be int32, got {perms.dtype}")
+    if not perms.is_contiguous():
+        raise OtmError(-1, "perms must be contiguous")
+    if perm_stride < 0:
+        raise OtmError(-1, "perm_stride must be >= 0")
+    need = (restarts - 1) * perm_stride + passes * n
+    if perms.numel() < need:
+        raise OtmError(-2, f"perms holds {perms.numel()} entries, the runs read {need} "
+                           f"((restarts-1)*perm_stride + passes*n)")
+
+
 def sgd_run(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, perms: torch.Tensor | None, Phi: torch.Tensor,
             restarts: int = 1, perm_stride: int = 0, start_step: int = 0, end_step: int = -1,
             Phi_comp: torch.Tensor | None = None, snapshots: torch.Tensor | None = None,
             nonfinite: torch.Tensor | None = None, stream=None):
     """Runs STGD steps [start_step, end_step) for `restarts` independent runs
     (Phi: restarts x k x k FP32, updated in place)."""
+    check_perms(perms, n, p.passes, restarts, perm_stride)
     cp = p.c()
     _check(lib().otm_sgd_run(ctypes.byref(cp), n, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), _ptr(perms),
                              perm_stride, restarts, start_step, end_step, _ptr(Phi), _ptr(Phi_comp),
@@ -395,6 +644,7 @@ class BatchedRun:
                 raise OtmError(-2, "Phi0 must be restarts x k x k")
             # perms: restarts x passes x n (one order per run) or passes x n (shared)
             stride = 0 if P.perms is None or P.perms.dim() == 2 else P.perms[0].numel()
+            check_perms(P.perms, n, p.passes, restarts, stride)
             arr[i] = _Problem(_ptr(P.YA), _ptr(P.YB), _ptr(P.YC), _ptr(P.ybar3), _ptr(P.perms), stride,
                               _ptr(P.Phi0), _ptr(self.Phi[i]), _ptr(self.scores[i]), n, P.k, ldy, 0,
                               float(P.alpha0))
@@ -449,17 +699,18 @@ def sgd_autotune(ks, batch: int, cache_path: str, stream=None):
 
 
 # ------------------------------------------------------------------ a6
-def unwhiten_topics(W: torch.Tensor, Phi: torch.Tensor, theta: float = 1.0, stream=None):
+def unwhiten_topics(W: torch.Tensor, Phi: torch.Tensor, theta: float = 1.0, stream=None,
+                    info: torch.Tensor | None = None):
     d, k = W.shape
     mu = torch.empty((d, k), dtype=torch.float64, device=W.device)
     ah = torch.empty(k, dtype=torch.float64, device=W.device)
     lam = torch.empty(k, dtype=torch.float64, device=W.device)
-    info = torch.zeros(1, dtype=torch.int32, device=W.device)
+    info, deferred = _info_slot(info, W.device)
     ws = _ws(lib().otm_unwhiten_workspace(d, k), W.device)
     _check(lib().otm_unwhiten_topics(_ptr(W), d, k, _ptr(Phi), float(theta), _ptr(mu), _ptr(ah), _ptr(lam),
                                      _ptr(info), _ptr(ws), ws.numel(), _stream(stream)))
-    if int(info.item()) != 0:
-        raise OtmError(-4, "W^T W is not positive definite")
+    if not deferred and int(info.item()) != 0:
+        _raise_info("unwhiten_topics")
     return mu, ah, lam
 
 
@@ -470,6 +721,47 @@ def recover_pi(Y: torch.Tensor, k: int, Phi: torch.Tensor, theta: float = 1.0, t
     _check(lib().otm_recover_pi(_ptr(Y), _DTYPE_CODE[Y.dtype], ldy, n, k, _ptr(Phi), float(theta), float(tau),
                                 _ptr(Pi), _ptr(ws), ws.numel(), _stream(stream)))
     return Pi
+
+
+# ------------------------------------------------------------------ validation
+@dataclass
+class Validation:
+    rho: torch.Tensor
+    p: torch.Tensor
+    p_adj: torch.Tensor
+    edges: torch.Tensor
+    l1: torch.Tensor
+    scores: torch.Tensor        # [recovery ratio, error]
+
+
+def validate(Pi_hat: torch.Tensor, Pi: torch.Tensor, threshold: float = 0.01, stream=None) -> Validation:
+    """p-value matching of estimated to true communities and the recovery
+    ratio / error (FP32 k_hat x n and k x n inputs, FP64 results)."""
+    kh, n = Pi_hat.shape
+    k = Pi.shape[0]
+    if Pi.shape[1] != n or Pi_hat.dtype != torch.float32 or Pi.dtype != torch.float32:
+        raise OtmError(-2, "Pi_hat and Pi must be FP32 with the same number of nodes")
+    dev = Pi_hat.device
+    out = [torch.empty((kh, k), dtype=torch.float64, device=dev) for _ in range(3)]
+    edges = torch.empty((kh, k), dtype=torch.int32, device=dev)
+    l1 = torch.empty((kh, k), dtype=torch.float64, device=dev)
+    scores = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = _ws(lib().otm_validate_workspace(kh, k, n), dev)
+    _check(lib().otm_validate(_ptr(Pi_hat), kh, _ptr(Pi), k, n, float(threshold), _ptr(out[0]), _ptr(out[1]),
+                              _ptr(out[2]), _ptr(edges), _ptr(l1), _ptr(scores), _ptr(ws), ws.numel(),
+                              _stream(stream)))
+    return Validation(out[0], out[1], out[2], edges, l1, scores)
+
+
+def bridgeness(Pi_hat: torch.Tensor, G: DeviceCSR | None = None, stream=None):
+    """(b, b_degree or None) per node."""
+    kh, n = Pi_hat.shape
+    b = torch.empty(n, dtype=torch.float64, device=Pi_hat.device)
+    bd = torch.empty(n, dtype=torch.float64, device=Pi_hat.device) if G is not None else None
+    gc = G.c() if G is not None else None
+    _check(lib().otm_bridgeness(_ptr(Pi_hat), kh, n, ctypes.byref(gc) if gc is not None else None, _ptr(b), _ptr(bd),
+                                _stream(stream)))
+    return b, bd
 
 
 # ------------------------------------------------------------------ loss

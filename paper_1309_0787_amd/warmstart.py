@@ -157,3 +157,91 @@ class WarmStart:
         out = self.infer(X, bf16)
         Phi = otm.ws_factors(ks, out, Q, sigma)
         return Phi[0, :k * k].reshape(k, k)
+
+
+# ---------------------------------------------------------------------------
+# Training and held-out instances drawn from the three workloads' generators
+# ---------------------------------------------------------------------------
+FAMILIES = {
+    # the graph and document workloads: components, samples, Dirichlet total
+    "mmsb_small": dict(k=10, n=500, alpha0=0.1),
+    "lda_medium": dict(k=50, n=100000, alpha0=1.0),
+    "mmsb_large": dict(k=100, n=50000, alpha0=0.5),
+}
+
+
+def family_weights(family: str, seed: int) -> np.ndarray:
+    """Community shares of a workload's samples as its generator draws them:
+    memberships pi ~ Dir(alpha0/k 1) for its n samples (Section 2), each
+    sample taken in its largest community (the block-model limit, which keeps
+    the whitened third moment exactly orthogonal); returns alpha_hat_j, the
+    share of community j (empty communities get one sample)."""
+    import synth
+    f = FAMILIES[family]
+    k, n = f["k"], f["n"]
+    g = synth.rng(seed, synth.S_MISC, 31)
+    pi = g.dirichlet(np.full(k, f["alpha0"] / k), size=n)
+    counts = np.bincount(np.argmax(pi, axis=1), minlength=k).astype(np.float64)
+    counts = np.maximum(counts, 1.0)
+    return counts / counts.sum()
+
+
+def generated_exact_instance(family: str, seed: int):
+    """Exact moments of a block model from a workload's generator, in
+    whitened coordinates: T = sum_j lambda_j u_j^(x3), lambda_j =
+    alpha_hat_j^(-1/2) from family_weights, U Haar (the whitened basis is
+    arbitrary, Section 3.1); the k rows y_j = (k lambda_j)^(1/3) u_j with
+    alpha0 = 0 have exactly this tensor.  Returns (Y, U, lam) as numpy."""
+    import synth
+    ahat = family_weights(family, seed)
+    k = ahat.size
+    lam = ahat ** -0.5
+    U = synth.initial_factors(k, seed=seed, restart=78)
+    Y = np.ascontiguousarray((U * np.cbrt(k * lam)[None, :]).T, dtype=np.float32)
+    return Y, U, lam
+
+
+def build_generated(specs: list[dict], device, sampled_pool=None, P: int | None = None) -> InstanceSet:
+    """specs: dicts with family and seed, kind 'exact' (generated_exact_instance)
+    or 'sampled': rows[i] of a whitened sample pool (sampled_pool: dict with Y
+    (n x ldy FP32, device), U (k x k planted directions in the whitened
+    coordinates), lam (k), alpha0) restricted to a seeded subset of size
+    spec['n'].  Sketches run on the GPU."""
+    P = P or otm.ws_dims()["P"]
+    cnt = len(specs)
+    ks = torch.zeros(cnt, dtype=torch.int32, device=device)
+    S = torch.zeros((cnt, 4, P, P), dtype=torch.float32, device=device)
+    Th = torch.zeros((cnt, P, 4), dtype=torch.float32, device=device)
+    U = torch.zeros((cnt, P, P), dtype=torch.float32, device=device)
+    lam = torch.zeros((cnt, P), dtype=torch.float32, device=device)
+    kk = []
+    for i, s in enumerate(specs):
+        if s.get("kind", "exact") == "exact":
+            Y, Ui, li = generated_exact_instance(s["family"], s["seed"])
+            k = Y.shape[0]
+            YA = YB = YC = torch.as_tensor(Y, device=device)
+            a0 = 0.0
+        else:
+            pool = sampled_pool
+            k = pool["U"].shape[0]
+            g = np.random.default_rng([s["seed"], 11])
+            rows = torch.as_tensor(np.sort(g.choice(pool["Y"].shape[0], s["n"], replace=False)), device=device)
+            YA = YB = YC = pool["Y"].index_select(0, rows).contiguous()
+            Ui, li, a0 = pool["U"], pool["lam"], pool["alpha0"]
+        kk.append(k)
+        ybar = torch.stack([YA[:, :k].mean(0), YB[:, :k].mean(0), YC[:, :k].mean(0)]).contiguous()
+        th = torch.as_tensor(_thetas(k, s["seed"], P), device=device)
+        Th[i] = th
+        otm.ws_sketch(YA, YB, YC, k, ybar, a0, th[:k].contiguous(), S[i])
+        U[i, :k, :k] = torch.as_tensor(np.asarray(Ui), dtype=torch.float32, device=device)
+        lam[i, :k] = torch.as_tensor(np.asarray(li), dtype=torch.float32, device=device)
+    ks.copy_(torch.tensor(kk, dtype=torch.int32))
+    return InstanceSet(ks, S, Th, U, lam)
+
+
+def warm_factors_batch(warm: "WarmStart", inst: InstanceSet, bf16: bool = True) -> torch.Tensor:
+    """Warm-start factors of every instance of a set (count x P*P, instance i's
+    phi_j at row i, offset j*k), from the set's own sketches."""
+    Q, sigma, X, info = otm.ws_frames(inst.ks, inst.S, inst.Theta)
+    out = warm.infer(X, bf16)
+    return otm.ws_factors(inst.ks, out, Q, sigma)

@@ -100,6 +100,10 @@ def _pairs_lib():
     p = ctypes.c_void_p
     lib.mmsb_count.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, p, p, p, p]
     lib.mmsb_fill.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, p, p, p, p, p]
+    g = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+         ctypes.c_uint64, p, p, p, p, p, p]
+    lib.pairs_count.argtypes = g + [p]
+    lib.pairs_fill.argtypes = g + [p, p, p]
     return lib
 
 
@@ -125,17 +129,9 @@ class MMSBInstance:
     meta: dict = field(default_factory=dict)
 
 
-def mmsb(n: int, k: int, alpha0: float, p: float, q: float, n_x: int | None = None,
-         seed: int = BASE_SEED, pi_floor: float = 1e-15) -> MMSBInstance:
-    """Draw an MMSB graph and its X/A split.
-
-    pi_floor: membership entries below it are dropped from the edge
-    probabilities (each dropped term changes a probability by < pi_floor).
-    """
-    alpha = np.full(k, alpha0 / k)
-    pi = rng(seed, S_PI).dirichlet(alpha, size=n)
-    P = np.full((k, k), q) + (p - q) * np.eye(k)
-    # sparse membership lists for the sampler
+def _mmsb_edges(n: int, pi: np.ndarray, p: float, q: float, seed: int, pi_floor: float):
+    """Undirected edge list (src < dst) of the Bernoulli MMSB with
+    P = q 1 1^T + (p - q) I, sampled by the C helper."""
     mask = pi >= pi_floor
     pptr = np.zeros(n + 1, dtype=np.int64)
     pptr[1:] = np.cumsum(mask.sum(1))
@@ -152,26 +148,171 @@ def mmsb(n: int, k: int, alpha0: float, p: float, q: float, n_x: int | None = No
     upper = np.zeros(int(offsets[-1]), dtype=np.int32)
     lib.mmsb_fill(n, p, q, eseed, ptr(pptr), ptr(pidx), ptr(pval), ptr(offsets), ptr(upper))
     src = np.repeat(np.arange(n, dtype=np.int64), counts)
-    dst = upper.astype(np.int64)
+    return src, upper.astype(np.int64)
+
+
+def _sparse_memberships(pi: np.ndarray, pi_floor: float):
+    mask = pi >= pi_floor
+    ptr = np.zeros(pi.shape[0] + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(mask.sum(1))
+    rows, cols = np.nonzero(mask)
+    return ptr, cols.astype(np.int32), pi[rows, cols].astype(np.float64)
+
+
+def _pairs_general(pi_rows: np.ndarray, pi_cols: np.ndarray, triangular: bool, poisson: bool, p: float, q: float,
+                   eseed: int, pi_floor: float):
+    """Edges (row index, column index, weight) between two node sets (or
+    within one set, j > i, when triangular) under the Bernoulli or Poisson
+    model with P = q 1 1^T + (p - q) I, sampled by the C helper."""
+    lib = _pairs_lib()
+    rp, ri, rv = _sparse_memberships(pi_rows, pi_floor)
+    cp, ci, cv = _sparse_memberships(pi_cols, pi_floor)
+    nr, nc = pi_rows.shape[0], pi_cols.shape[0]
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    counts = np.zeros(nr, dtype=np.int64)
+    args = (nr, nc, int(triangular), int(poisson), p, q, eseed, ptr(rp), ptr(ri), ptr(rv), ptr(cp), ptr(ci), ptr(cv))
+    lib.pairs_count(*args, ptr(counts))
+    offsets = np.zeros(nr + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    cols = np.zeros(int(offsets[-1]), dtype=np.int32)
+    w = np.zeros(int(offsets[-1]), dtype=np.float32)
+    lib.pairs_fill(*args, ptr(offsets), ptr(cols), ptr(w))
+    src = np.repeat(np.arange(nr, dtype=np.int64), counts)
+    return src, cols.astype(np.int64), w
+
+
+def graph_block(src: np.ndarray, dst: np.ndarray, n: int, rows: np.ndarray, cols: np.ndarray,
+                weights: np.ndarray | None = None) -> CSR:
+    """G[rows, cols] of the undirected graph with edges (src, dst) (both
+    directions), rows and cols sorted node ids; implicit ones unless weights."""
+    import scipy.sparse as sp
+    pos_r = np.full(n, -1, dtype=np.int64)
+    pos_r[rows] = np.arange(len(rows))
+    pos_c = np.full(n, -1, dtype=np.int64)
+    pos_c[cols] = np.arange(len(cols))
+    r = np.concatenate([src, dst])
+    c = np.concatenate([dst, src])
+    keep = (pos_r[r] >= 0) & (pos_c[c] >= 0)
+    w = np.ones(int(keep.sum()), dtype=np.float32) if weights is None else \
+        np.concatenate([weights, weights]).astype(np.float32)[keep]
+    m = sp.csr_matrix((w, (pos_r[r[keep]], pos_c[c[keep]])), shape=(len(rows), len(cols)))
+    return CSR.from_scipy(m, implicit_ones=weights is None)
+
+
+def mmsb(n: int, k: int, alpha0: float, p: float, q: float, n_x: int | None = None,
+         seed: int = BASE_SEED, pi_floor: float = 1e-15) -> MMSBInstance:
+    """Draw an MMSB graph and its X/A split.
+
+    pi_floor: membership entries below it are dropped from the edge
+    probabilities (each dropped term changes a probability by < pi_floor).
+    """
+    alpha = np.full(k, alpha0 / k)
+    pi = rng(seed, S_PI).dirichlet(alpha, size=n)
+    P = np.full((k, k), q) + (p - q) * np.eye(k)
+    src, dst = _mmsb_edges(n, pi, p, q, seed, pi_floor)
     # split nodes
     n_x = n // 2 if n_x is None else n_x
     perm = rng(seed, S_PARTITION).permutation(n)
     X = np.sort(perm[:n_x])
     A = np.sort(perm[n_x:])
-    pos_x = np.full(n, -1, dtype=np.int64)
-    pos_x[X] = np.arange(len(X))
-    pos_a = np.full(n, -1, dtype=np.int64)
-    pos_a[A] = np.arange(len(A))
-    # both directions of every undirected edge, kept where row in X and col in A
-    r = np.concatenate([src, dst])
-    c = np.concatenate([dst, src])
-    keep = (pos_x[r] >= 0) & (pos_a[c] >= 0)
-    import scipy.sparse as sp
-    m = sp.csr_matrix((np.ones(int(keep.sum()), dtype=np.float32), (pos_x[r[keep]], pos_a[c[keep]])),
-                      shape=(len(X), len(A)))
-    C = CSR.from_scipy(m, implicit_ones=True)
+    C = graph_block(src, dst, n, X, A)
     return MMSBInstance(n=n, k=k, alpha=alpha, P=P, pi=pi, X=X, A=A, C=C, CT=C.transpose(),
                         n_edges=int(len(src)), meta=dict(alpha0=alpha0, p=p, q=q, seed=seed))
+
+
+@dataclass
+class MMSBFour:
+    """An MMSB graph with its nodes split into the sample set X and the three
+    leaf sets A, B, C of Section 2.2.  blocks[(R, S)] = G[R, S] (CSR) for the
+    pairs the method reads: (X,A), (X,B), (X,C), their transposes, and
+    (B,A), (C,A) for the memberships of the B and C nodes."""
+    n: int
+    k: int
+    alpha: np.ndarray
+    P: np.ndarray
+    pi: np.ndarray
+    sets: dict                 # name -> sorted node ids
+    blocks: dict
+    n_edges: int = 0
+    meta: dict = field(default_factory=dict)
+
+
+FOUR_BLOCKS = (("X", "A"), ("X", "B"), ("X", "C"), ("A", "X"), ("B", "X"), ("C", "X"), ("B", "A"), ("C", "A"),
+               ("A", "B"), ("A", "C"))
+
+
+def mmsb_four(n: int, k: int, alpha0: float, p: float, q: float, fractions=(0.25, 0.25, 0.25, 0.25),
+              seed: int = BASE_SEED, pi_floor: float = 1e-15, poisson: bool = False) -> MMSBFour:
+    """The same Bernoulli MMSB as mmsb() (same memberships and edges for the
+    same seed), or the Poisson model's counts (as mmsb_weighted()), with the
+    nodes split at random into X, A, B, C of the given fractions (Section 2.2)."""
+    alpha = np.full(k, alpha0 / k)
+    pi = rng(seed, S_PI).dirichlet(alpha, size=n)
+    P = np.full((k, k), q) + (p - q) * np.eye(k)
+    w = None
+    if poisson:
+        eseed = int(rng(seed, S_EDGES, 1).integers(0, 2**63 - 1))
+        src, dst, w = _pairs_general(pi, pi, True, True, p, q, eseed, pi_floor)
+    else:
+        src, dst = _mmsb_edges(n, pi, p, q, seed, pi_floor)
+    perm = rng(seed, S_PARTITION, 4).permutation(n)
+    sizes = [int(round(f * n)) for f in fractions[:3]]
+    cuts = np.cumsum([0] + sizes + [n - sum(sizes)])
+    sets = {name: np.sort(perm[cuts[i]:cuts[i + 1]]) for i, name in enumerate("XABC")}
+    blocks = {(r, c): graph_block(src, dst, n, sets[r], sets[c], weights=w) for r, c in FOUR_BLOCKS}
+    return MMSBFour(n=n, k=k, alpha=alpha, P=P, pi=pi, sets=sets, blocks=blocks, n_edges=int(len(src)),
+                    meta=dict(alpha0=alpha0, p=p, q=q, seed=seed, model="poisson" if poisson else "bernoulli"))
+
+
+def mmsb_weighted(n: int, k: int, alpha0: float, p: float, q: float, n_x: int | None = None,
+                  seed: int = BASE_SEED, pi_floor: float = 1e-15) -> MMSBInstance:
+    """The Poisson model of Section 2.2 (weighted edges): undirected counts
+    G_ij ~ Poisson(pi_i^T P pi_j), P = q 1 1^T + (p - q) I, no self-loops; the
+    observed G[X, A] carries the counts as values."""
+    alpha = np.full(k, alpha0 / k)
+    pi = rng(seed, S_PI).dirichlet(alpha, size=n)
+    P = np.full((k, k), q) + (p - q) * np.eye(k)
+    eseed = int(rng(seed, S_EDGES, 1).integers(0, 2**63 - 1))
+    src, dst, w = _pairs_general(pi, pi, True, True, p, q, eseed, pi_floor)
+    n_x = n // 2 if n_x is None else n_x
+    perm = rng(seed, S_PARTITION).permutation(n)
+    X = np.sort(perm[:n_x])
+    A = np.sort(perm[n_x:])
+    C = graph_block(src, dst, n, X, A, weights=w)
+    return MMSBInstance(n=n, k=k, alpha=alpha, P=P, pi=pi, X=X, A=A, C=C, CT=C.transpose(), n_edges=int(len(src)),
+                        meta=dict(alpha0=alpha0, p=p, q=q, seed=seed, model="poisson"))
+
+
+@dataclass
+class BipartiteInstance:
+    """A bipartite graph between node sets U (rows) and V (columns), both with
+    Dirichlet memberships over the same k communities (the business-user
+    setting of Section 6): C = G[U, V], CT = G[V, U]."""
+    k: int
+    alpha: np.ndarray
+    P: np.ndarray
+    pi_u: np.ndarray
+    pi_v: np.ndarray
+    C: CSR
+    CT: CSR
+    meta: dict = field(default_factory=dict)
+
+
+def bipartite(n_u: int, n_v: int, k: int, alpha0: float, p: float, q: float, poisson: bool = True,
+              seed: int = BASE_SEED, pi_floor: float = 1e-15) -> BipartiteInstance:
+    """G[u, v] ~ Poisson (or Bernoulli) of pi_u^T P pi_v for every u in U, v in V,
+    no edge inside a side."""
+    import scipy.sparse as sp
+    alpha = np.full(k, alpha0 / k)
+    pi_u = rng(seed, S_PI, 1).dirichlet(alpha, size=n_u)
+    pi_v = rng(seed, S_PI, 2).dirichlet(alpha, size=n_v)
+    P = np.full((k, k), q) + (p - q) * np.eye(k)
+    eseed = int(rng(seed, S_EDGES, 2).integers(0, 2**63 - 1))
+    src, dst, w = _pairs_general(pi_u, pi_v, False, poisson, p, q, eseed, pi_floor)
+    m = sp.csr_matrix((w if poisson else np.ones_like(w), (src, dst)), shape=(n_u, n_v))
+    C = CSR.from_scipy(m, implicit_ones=not poisson)
+    return BipartiteInstance(k=k, alpha=alpha, P=P, pi_u=pi_u, pi_v=pi_v, C=C, CT=C.transpose(),
+                             meta=dict(alpha0=alpha0, p=p, q=q, seed=seed, poisson=poisson))
 
 
 # --------------------------------------------------------------------------
@@ -248,6 +389,23 @@ def lda(d: int, k: int, alpha0: float, beta: float, n_docs: int, mean_len: float
 def projection(d: int, k_tilde: int, seed: int = BASE_SEED) -> np.ndarray:
     """Dense Gaussian projection S (d x k_tilde), FP64, row-major."""
     return rng(seed, S_PROJ).standard_normal((d, k_tilde))
+
+
+def column_selection(d: int, k_tilde: int, seed: int = BASE_SEED):
+    """Column-selection projection with random signs (for a sparse M2,
+    Section 4.2): k_tilde distinct rows r_j of [d] and signs s_j in {-1, +1};
+    S[r_j, j] = s_j and every other entry 0.  Returns (rows int32, signs FP64)."""
+    g = rng(seed, S_PROJ, 7)
+    rows = g.choice(d, size=k_tilde, replace=False).astype(np.int32)
+    signs = np.where(g.random(k_tilde) < 0.5, -1.0, 1.0)
+    return rows, signs
+
+
+def selection_dense(rows: np.ndarray, signs: np.ndarray, d: int) -> np.ndarray:
+    """The d x k_tilde matrix of a column selection."""
+    S = np.zeros((d, len(rows)))
+    S[rows, np.arange(len(rows))] = signs
+    return S
 
 
 def initial_factors(k: int, seed: int = BASE_SEED, restart: int = 0) -> np.ndarray:

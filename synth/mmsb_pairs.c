@@ -99,3 +99,86 @@ void mmsb_fill(int64_t n, double p, double q, uint64_t seed,
     for (int64_t i = 0; i < n; ++i)
         walk_row(i, n, p, q, seed, pptr, pidx, pval, cols + offsets[i]);
 }
+
+/*
+ * Generalised sampler: row node i of a row set against the nodes j of a
+ * column set (both with sparse membership lists).  triangular != 0: one node
+ * set, pairs j > i only (an undirected graph); otherwise every j (a bipartite
+ * graph between two node sets).
+ *
+ * poisson == 0: Bernoulli(q + (p - q) <pi_i, pi_j>) edges as above.
+ * poisson != 0: the Poisson model of Section 2.2, counts
+ * G_ij ~ Poisson(lambda_ij), lambda_ij = q + (p - q) <pi_i, pi_j> <= p: every
+ * pair holds Poisson(p) candidates, each kept with probability lambda_ij / p
+ * (thinning), so the kept count is Poisson(lambda_ij).  Pairs with at least
+ * one candidate (probability 1 - e^-p) are reached by geometric skipping;
+ * their candidate count is drawn from the Poisson(p) law conditioned on >= 1
+ * by inversion.  A pair with a kept count >= 1 is an edge of that weight.
+ *
+ * Randomness: one splitmix64 stream per row keyed by (seed, row).
+ */
+static int64_t walk_row_gen(int64_t i, int64_t n_cols, int triangular, int poisson, double p, double q, uint64_t seed,
+                            const int64_t* rptr, const int32_t* ridx, const double* rval,
+                            const int64_t* cptr, const int32_t* cidx, const double* cval,
+                            int32_t* out_cols, float* out_w) {
+    row_rng r = rng_for_row(seed, i);
+    const double hit = poisson ? -expm1(-p) : p;          /* P(pair has >= 1 candidate) */
+    const double log1mh = log1p(-hit);
+    int64_t j = triangular ? i : -1;
+    int64_t cnt = 0;
+    const int32_t* ia = ridx + rptr[i];
+    const double* va = rval + rptr[i];
+    const int na = (int)(rptr[i + 1] - rptr[i]);
+    for (;;) {
+        double u = next_u01(&r);
+        double skip = (hit >= 1.0) ? 0.0 : floor(log(u) / log1mh);
+        if (skip > (double)n_cols) break;
+        j += 1 + (int64_t)skip;
+        if (j >= n_cols) break;
+        double s = sparse_dot(ia, va, na, cidx + cptr[j], cval + cptr[j], (int)(cptr[j + 1] - cptr[j]));
+        double acc = (q + (p - q) * s) / p;
+        int kept = 0;
+        if (poisson) {
+            /* candidates: Poisson(p) given >= 1, by inversion */
+            double v = next_u01(&r);
+            double term = p * exp(-p) / hit, cdf = term;
+            int m = 1;
+            while (v > cdf && m < 1000) {
+                ++m;
+                term *= p / m;
+                cdf += term;
+            }
+            for (int c = 0; c < m; ++c)
+                if (next_u01(&r) <= acc) ++kept;
+        } else {
+            kept = next_u01(&r) <= acc ? 1 : 0;
+        }
+        if (kept > 0) {
+            if (out_cols) {
+                out_cols[cnt] = (int32_t)j;
+                if (out_w) out_w[cnt] = (float)kept;
+            }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+void pairs_count(int64_t n_rows, int64_t n_cols, int triangular, int poisson, double p, double q, uint64_t seed,
+                 const int64_t* rptr, const int32_t* ridx, const double* rval,
+                 const int64_t* cptr, const int32_t* cidx, const double* cval, int64_t* counts) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_rows; ++i)
+        counts[i] = walk_row_gen(i, n_cols, triangular, poisson, p, q, seed, rptr, ridx, rval, cptr, cidx, cval,
+                                 NULL, NULL);
+}
+
+void pairs_fill(int64_t n_rows, int64_t n_cols, int triangular, int poisson, double p, double q, uint64_t seed,
+                const int64_t* rptr, const int32_t* ridx, const double* rval,
+                const int64_t* cptr, const int32_t* cidx, const double* cval,
+                const int64_t* offsets, int32_t* cols, float* weights) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_rows; ++i)
+        walk_row_gen(i, n_cols, triangular, poisson, p, q, seed, rptr, ridx, rval, cptr, cidx, cval,
+                     cols + offsets[i], weights ? weights + offsets[i] : NULL);
+}

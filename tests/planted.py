@@ -40,3 +40,25 @@ def planted_whitened_factors(W: np.ndarray, F: np.ndarray, ahat: np.ndarray):
     U = (W.T @ F) * np.sqrt(ahat)[None, :]
     lam = ahat ** -0.5
     return U, lam, U * np.cbrt(lam)[None, :]
+
+
+def planted_four(sizes: dict, k: int, p: float, q: float, seed: int, alpha0: float = 0.0):
+    """Exact-moment four-partition graph (Section 2.2): node memberships pi
+    (pure, every community present in every set, when alpha0 = 0; else
+    Dir(alpha0/k)), P = q 1 1^T + (p - q) I, and the expected adjacency blocks
+    E[G[R, S]] = Pi_R^T P Pi_S as dense matrices (sparse containers).
+    Returns (pi per set (k x n_set), P, blocks)."""
+    import scipy.sparse as sp
+    g = synth.rng(seed, synth.S_MISC, 7)
+    P = np.full((k, k), q) + (p - q) * np.eye(k)
+    pis = {}
+    for name, n in sizes.items():
+        if alpha0 == 0.0:
+            lab = g.permutation(np.arange(n) % k)
+            pis[name] = np.eye(k)[:, lab]
+        else:
+            pis[name] = g.dirichlet(np.full(k, alpha0 / k), size=n).T
+    blocks = {}
+    for r, c in synth.FOUR_BLOCKS:
+        blocks[(r, c)] = sp.csr_matrix(pis[r].T @ P @ pis[c])
+    return pis, P, blocks

@@ -8,11 +8,14 @@ one or on properties that hold at any size.
   the same BF16 W (one BF16 rounding of the FP32 accumulators: 8e-3 per row);
   the means 1e-6; one STGD step of the benchmark's kernel
   (sgd_kernel<BF16, 128, staged>) from a pass-end snapshot against the oracle
-  step on the same BF16 rows (the BF16 step bar 3e-2); the residual of the
-  full 50-pass BF16 run within 0.01 of the FP64 oracle run's.
+  step on the same BF16 rows (the BF16 step bar 3e-2); the full 50-pass BF16
+  run (25,000 steps) against the FP64 oracle run from the same initial
+  factors and permutations: relative factor error at most 1e-2 (the BF16 run
+  bar), and its residual within 2e-3 of the oracle run's.
 * Documents, d = 10000, k = 50, 100000 documents, FP32: sketch and whitener
-  (1e-8), three-view whitening on sampled rows (1e-6), one FP32 pass of
-  STGD against the oracle (factor error 1e-4).
+  (1e-8), three-view whitening on sampled rows (1e-6), the full 50-pass FP32
+  STGD run (50,000 steps) against the oracle run (factor error 1e-4, the FP32
+  bar), then the topic-word matrix and Dirichlet weights of both (1e-4).
 """
 import numpy as np
 import pytest
@@ -84,7 +87,8 @@ def test_graph_stgd_step_and_run_fullsize(graph):
     yb = np.stack([host(ybar)] * 3)
     ref = oracle.sgd_step(Yh[rows], Yh[rows], Yh[rows], yb, f32_round(Phi_a), beta, 0.5)
     assert rel(Phi_b - Phi_a, ref - f32_round(Phi_a)) < 3e-2
-    # the whole 50-pass run: its residual against the FP64 oracle run's
+    # the whole 50-pass run (25,000 steps) against the FP64 oracle run from the
+    # same initial factors and permutations on the same BF16 rows: factor error
     Phi = to_dev(Phi0.T.copy(), torch.float32)[None].contiguous()
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")
     otm.sgd_run(p, n, Y, Y, Y, yb3, permd, Phi, nonfinite=flag)
@@ -94,7 +98,10 @@ def test_graph_stgd_step_and_run_fullsize(graph):
     Ro = oracle.sgd_run(Yh, Yh, Yh, yb, Phi0, perms, 100, 1e-3, 2500.0, 0.5)
     To = oracle.whitened_tensor(Yh, Yh, Yh, yb, 0.5)
     R_or = oracle.residual(To, Ro)
-    assert R_gpu < 0.1 and abs(R_gpu - R_or) < 0.01, (R_gpu, R_or)
+    err = rel(host(Phi[0]).T, Ro)
+    print(f"graph BF16 50-pass run: factor error {err:.3e}, R gpu {R_gpu:.5f} oracle {R_or:.5f}", flush=True)
+    assert err <= 1e-2, err
+    assert abs(R_gpu - R_or) < 2e-3, (R_gpu, R_or)
 
 
 def test_documents_fullsize():
@@ -121,13 +128,22 @@ def test_documents_fullsize():
         yrefs.append((f32_round(host(Yv)[:, :k]), f32_round(host(ybv))))
     yb3 = torch.cat([torch.as_tensor(y[1], dtype=torch.float32, device="cuda") for y in yrefs]).contiguous()
     n = inst.C.n_rows
-    perms = synth.permutations(n, 1, seed=3)
+    perms = synth.permutations(n, 50, seed=3)
     Phi0 = synth.initial_factors(k, seed=5)
-    p = otm.SgdParams(k=k, batch=100, passes=1, y_dtype=otm.F32, alpha0=1.0, beta0=1e-3, beta_tau=2500.0,
+    p = otm.SgdParams(k=k, batch=100, passes=50, y_dtype=otm.F32, alpha0=1.0, beta0=1e-3, beta_tau=2500.0,
                       ldy=views[0].shape[1])
     Phi = to_dev(Phi0.T.copy(), torch.float32)[None].contiguous()
-    otm.sgd_run(p, n, views[0], views[1], views[2], yb3, to_dev(perms, torch.int32), Phi)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    otm.sgd_run(p, n, views[0], views[1], views[2], yb3, to_dev(perms, torch.int32), Phi, nonfinite=flag)
+    mu_g, ah_g, _ = otm.unwhiten_topics(W, Phi[0])
     torch.cuda.synchronize()
+    assert int(flag.item()) == 0
     ref = oracle.sgd_run(yrefs[0][0], yrefs[1][0], yrefs[2][0], np.stack([y[1] for y in yrefs]), Phi0, perms, 100,
                          1e-3, 2500.0, 1.0)
-    assert rel(host(Phi[0]).T, ref) < 1e-4
+    err = rel(host(Phi[0]).T, ref)
+    print(f"documents FP32 50-pass run: factor error {err:.3e}", flush=True)
+    assert err <= 1e-4, err
+    # post-processing of both runs (Lemma postprocessing): topics and weights
+    mu_o, ah_o, _ = oracle.unwhiten_topics(Wo, ref)
+    assert rel(host(mu_g), mu_o) <= 1e-4
+    np.testing.assert_allclose(host(ah_g), ah_o, rtol=1e-4)

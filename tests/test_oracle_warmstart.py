@@ -145,3 +145,31 @@ def test_greedy_match():
     # greedy, not optimal: the largest entry is taken first
     C = np.array([[0.9, 0.8], [0.85, 0.1]])
     np.testing.assert_array_equal(ws.greedy_match(C), [0, 1])
+
+
+def test_sketch_scale_exact_values():
+    """sigma = sqrt(mean_r ||S_r||_F^2) on hand-built sketches: squared norms
+    2, 8, 0 and 25 give sqrt(35 / 4) (a sum in place of the mean, or a norm
+    in place of its square, gives another number)."""
+    S = np.zeros((4, 2, 2))
+    S[0] = np.eye(2)
+    S[1] = 2.0 * np.eye(2)
+    S[3] = [[3.0, 0.0], [4.0, 0.0]]
+    assert ws.sketch_scale(S) == pytest.approx(np.sqrt(35.0 / 4.0), rel=1e-15)
+    assert ws.sketch_scale(np.zeros((4, 3, 3))) == 0.0
+
+
+def test_sketch_scale_is_the_tensor_norm_for_an_orthonormal_design():
+    """For T = sum_l lambda_l u_l^(x3) (k = 4) and theta_r = 2 u_r,
+    ||T(I, I, theta_r)||_F^2 = 4 lambda_r^2, so the mean over the four
+    sketches is sum_l lambda_l^2 = ||T||_F^2 exactly: sigma = ||T||_F."""
+    k = 4
+    lam = np.array([1.0, 2.0, 3.0, 4.0])
+    U = synth.initial_factors(k, seed=21)
+    Y = (U * np.cbrt(k * lam)[None, :]).T.copy()          # exact samples, alpha0 = 0
+    ybar = np.stack([Y.mean(0)] * 3)
+    Theta = 2.0 * U
+    S = ws.sketch(Y, Y, Y, ybar, 0.0, Theta)
+    assert ws.sketch_scale(S) == pytest.approx(np.sqrt(30.0), rel=1e-13)
+    T = oracle.whitened_tensor(Y, Y, Y, ybar, 0.0)
+    assert ws.sketch_scale(S) == pytest.approx(np.sqrt(np.sum(T * T)), rel=1e-13)

@@ -119,3 +119,76 @@ def test_sampled_graph_whitener_invariant_on_low_rank_m2():
     idx = np.argsort(-sig)[:4]
     B = O @ U[:, idx] / np.sqrt(sig[idx])
     np.testing.assert_allclose(W.T @ (B @ B.T) @ W, np.eye(4), atol=1e-11)
+
+
+def _principal_angle_max(A: np.ndarray, B: np.ndarray) -> float:
+    """Sine of the largest principal angle between span(A) and span(B) (equal
+    widths): the spectral norm of the part of B's basis outside span(A)."""
+    Qa = np.linalg.qr(A)[0]
+    Qb = np.linalg.qr(B)[0]
+    return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
+
+
+@pytest.mark.parametrize("q", [0, 1, 3])
+def test_power_sketch_steps_against_dense_m2(q):
+    """The power-iterated sketch (reading of Section 4.2 for sampled moments),
+    checked against the explicitly formed M2 of a sampled graph: the returned
+    O is M2 applied to the returned Q, Q has orthonormal columns (q >= 1;
+    q = 0 returns S itself), and span(Q) is span(M2^q S), the q-th Krylov
+    image of the projection (an extra or missing iteration moves the span)."""
+    g = synth.make("mmsb_small")
+    d = g.C.n_cols
+    M2 = oracle.m2_apply(g.C, np.eye(d), 0.1, False)
+    # the explicit M2 is the pair enumeration's: symmetric, as Section 2.2 defines it
+    np.testing.assert_allclose(M2, M2.T, atol=1e-14)
+    S = synth.projection(d, 20, seed=1)
+    Q, O = oracle.power_sketch(g.C, S, 0.1, False, q)
+    np.testing.assert_allclose(O, M2 @ Q, atol=1e-12 * np.abs(M2 @ Q).max())
+    if q == 0:
+        np.testing.assert_array_equal(Q, S)
+    else:
+        np.testing.assert_allclose(Q.T @ Q, np.eye(20), atol=1e-12)
+    K = S.copy()
+    for _ in range(q):
+        K = M2 @ K
+    assert _principal_angle_max(Q, K) < 1e-10
+    # the spans of neighbouring iteration counts are far apart on this graph
+    if q >= 1:
+        assert _principal_angle_max(Q, np.linalg.matrix_power(M2, q - 1) @ S) > 1e-3
+    assert _principal_angle_max(Q, np.linalg.matrix_power(M2, q + 1) @ S) > 1e-3
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+def test_column_selection_sketch_is_signed_columns_of_m2(normalize):
+    """Section 4.2, sparse M2: with S a column selection with random signs,
+    O = M2 S holds the selected columns of M2 with their signs, and
+    S^T O holds the selected entries M2[r_i, r_j] s_i s_j."""
+    if normalize:
+        inst = synth.lda(d=40, k=3, alpha0=0.8, beta=0.3, n_docs=300, mean_len=12.0, seed=6)
+        C, a0 = inst.C, 0.8
+    else:
+        C, a0 = synth.mmsb(300, 3, 0.3, 0.4, 0.05, n_x=150, seed=6).C, 0.3
+    d = C.n_cols
+    M2 = oracle.m2_apply(C, np.eye(d), a0, normalize)
+    rows, signs = synth.column_selection(d, 9, seed=2)
+    S = synth.selection_dense(rows, signs, d)
+    assert len(set(rows.tolist())) == 9 and set(np.abs(signs)) == {1.0}
+    O = oracle.m2_apply(C, S, a0, normalize)
+    np.testing.assert_allclose(O, M2[:, rows] * signs[None, :], atol=1e-14 * np.abs(M2).max())
+    np.testing.assert_allclose(S.T @ O, M2[np.ix_(rows, rows)] * np.outer(signs, signs), atol=1e-14 * np.abs(M2).max())
+
+
+def test_whitener_with_column_selection_on_exact_rank_k():
+    """A column-selection sketch of width 2k of an exact rank-k M2 (whose
+    selected columns span its range) gives the whitener of the definition."""
+    d, k = 60, 5
+    mu, ahat = planted_topics(d, k, seed=31, beta=2.0)
+    M2 = exact_m2(mu, ahat)
+    rows, signs = synth.column_selection(d, 2 * k, seed=3)
+    S = synth.selection_dense(rows, signs, d)
+    W, evals = oracle.whitener_rsvd(M2 @ S, S, k)
+    np.testing.assert_allclose(W.T @ M2 @ W, np.eye(k), atol=1e-11)
+    lam, U = np.linalg.eigh(M2)
+    order = np.argsort(-lam)[:k]
+    W_def = oracle.canonical_signs(U[:, order] / np.sqrt(lam[order])[None, :])
+    np.testing.assert_allclose(W, W_def, atol=1e-9 * np.abs(W_def).max())
