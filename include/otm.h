@@ -239,6 +239,22 @@ int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_dtype, int3
                void* Y, int y_dtype, int32_t ldy, float* ybar,
                void* ws, size_t ws_bytes, otm_stream stream);
 
+/* The whitening SpMM of otm_whiten for callers that cannot allocate (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results (Y and ybar bit-identical to otm_whiten's),
+ * with the per-block partial column sums in a library-owned device array of
+ * otm_whiten_noalloc_capacity() floats (4 MiB, one copy per device, held until
+ * the process ends) instead of a caller workspace.  The call allocates
+ * nothing and takes no workspace; it returns OTM_EWORKSPACE when the partial
+ * sums (up to 8192 blocks x k) exceed the array, which never happens for
+ * k <= 128.  The first call on a device resolves the array's address there
+ * (make that call outside a graph capture).  All calls on one device share
+ * the array: calls that overlap on one device (several streams or host
+ * threads at once) race and give wrong ybar. */
+size_t otm_whiten_noalloc_capacity(void);
+int otm_whiten_noalloc(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
+                       void* Y, int y_dtype, int32_t ldy, float* ybar, otm_stream stream);
+
 /* ---- a4 / a5: stochastic tensor gradient descent (Section 3.2, Lemma
  * "update"; stacked form of Section 4.3) -----------------------------------
  * For a batch of rows t with whitened views yA_t, yB_t, yC_t (rows of YA,

@@ -22,6 +22,7 @@
 // Malformed CSR cannot make these kernels read out of bounds: row ranges are
 // clamped to [0, nnz] and entries with a column outside [0, n_cols) are skipped.
 #include <cmath>
+#include <mutex>
 
 #include "otm_internal.h"
 
@@ -707,6 +708,12 @@ __global__ void selection_dense_kernel(const int32_t* __restrict__ sel, const do
     S[idx] = (sel[j] == a) ? sgn[j] : 0.0;
 }
 
+// Scratch of the entry point that allocates nothing: the per-block column sums
+// of the whitening kernel (nblocks x k floats, at most 8192 x 128).  One copy
+// per device, resolved through hipGetSymbolAddress on the first call there.
+constexpr size_t kWhitenScratchFloats = size_t(1) << 20;   // 4 MiB
+static __device__ __align__(256) float scratch[kWhitenScratchFloats];
+
 // Y[row, :] = scale sum_j C[row, j] X[j, :]: the first M2 pass without its
 // weights (one wave per row, kM2Unroll entries loaded together, entries
 // summed in order).
@@ -842,6 +849,29 @@ int whiten_impl(const otm_csr* C, int normalize, const void* W, int w_dtype, int
     return OTM_OK;
 }
 
+// Device address of this device's copy of `scratch`, resolved once per device
+// (with that device current) and kept; the array's host-side name is not a
+// device address and is never passed to a kernel.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+int scratch_for_current_device(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    OTM_REQUIRE(dev >= 0 && dev < kMaxDevices, OTM_ECAPACITY, "device index beyond the scratch table (64)");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return OTM_OK;
+}
+
 }  // namespace
 }  // namespace otm
 
@@ -853,6 +883,17 @@ extern "C" int otm_whiten(const otm_csr* C, int normalize, const void* W, int w_
                 OTM_EWORKSPACE, "whiten workspace too small");
     return whiten_impl(C, normalize, W, w_dtype, k, ldw, Y, y_dtype, ldy, ybar, static_cast<float*>(ws),
                        ws_bytes / sizeof(float), as_stream(stream));
+}
+
+extern "C" size_t otm_whiten_noalloc_capacity(void) { return kWhitenScratchFloats; }
+
+extern "C" int otm_whiten_noalloc(const otm_csr* C, int normalize, const void* W, int w_dtype, int32_t k, int32_t ldw,
+                                  void* Y, int y_dtype, int32_t ldy, float* ybar, otm_stream stream) {
+    float* part = nullptr;
+    int st = scratch_for_current_device(&part);
+    if (st != OTM_OK) return st;
+    return whiten_impl(C, normalize, W, w_dtype, k, ldw, Y, y_dtype, ldy, ybar, part, kWhitenScratchFloats,
+                       as_stream(stream));
 }
 
 extern "C" size_t otm_m2_apply_workspace(int32_t n, int32_t d, int32_t k_tilde) {

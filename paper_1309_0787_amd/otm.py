@@ -97,6 +97,9 @@ _SIGS = {
     "otm_m2_apply_four": (ctypes.c_int, [ctypes.POINTER(_Partition), _vp, _vp, _vp, _i32, _dbl, _vp, _i32, _vp, _vp,
                                          _sz, _vp]),
     "otm_cast_rows": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.c_int, _i32, _vp]),
+    "otm_whiten_noalloc_capacity": (_sz, []),
+    "otm_whiten_noalloc": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _i32, _vp,
+                                          ctypes.c_int, _i32, _vp, _vp]),
     "otm_whiten_workspace": (_sz, [_i32, _i32]),
     "otm_whiten": (ctypes.c_int, [ctypes.POINTER(_CSR), ctypes.c_int, _vp, ctypes.c_int, _i32, _i32, _vp,
                                   ctypes.c_int, _i32, _vp, _vp, _sz, _vp]),
@@ -528,6 +531,20 @@ def whiten(C: DeviceCSR, normalize: bool, W: torch.Tensor, y_dtype: int = F32, l
     cc = C.c()
     _check(lib().otm_whiten(ctypes.byref(cc), int(normalize), w_ptr, _DTYPE_CODE[W.dtype], k, ldw, _ptr(Y),
                             y_dtype, ldy, _ptr(ybar), _ptr(ws), ws.numel(), _stream(stream)))
+    return Y, ybar
+
+
+def whiten_noalloc(C: DeviceCSR, normalize: bool, W: torch.Tensor, Y: torch.Tensor, ybar: torch.Tensor | None,
+                   y_dtype: int = F32, stream=None):
+    """otm_whiten_noalloc into caller-given Y (n x ldy) and ybar (k FP32 or
+    None): no workspace, nothing allocated by the library or here."""
+    d, k = W.shape
+    w_ptr, ldw = _ptr_rows(W)
+    if Y.dim() != 2 or Y.shape[0] != C.n_rows or Y.dtype != _TORCH_DTYPE[y_dtype]:
+        raise ValueError("Y must be n x ldy in y_dtype")
+    cc = C.c()
+    _check(lib().otm_whiten_noalloc(ctypes.byref(cc), int(normalize), w_ptr, _DTYPE_CODE[W.dtype], k, ldw, _ptr(Y),
+                                    y_dtype, Y.shape[1], _ptr(ybar), _stream(stream)))
     return Y, ybar
 
 
