@@ -201,14 +201,17 @@ BATCHED = dict(problems=256, ks=(16, 32, 64, 100, 128), n_lo=1e3, n_hi=1e5, rest
 PEAK_FP32_MFMA = 157.3e12
 
 
-def bench_batched(steps: int, warmup: int) -> dict:
-    """Many decompositions with restarts in one launch (FP32): 256 problems, k
-    uniform over {16, 32, 64, 100, 128}, n log-uniform in [1e3, 1e5], half
-    three-view (documents) and half one-view (graphs), 8 restarts each; the
-    tile layouts come from the autotuner (run first, timed separately)."""
+def bench_batched(steps: int, warmup: int, real_rows=None) -> dict:
+    """Many decompositions with restarts in one launch sequence (FP32): 256
+    problems, k uniform over {16, 32, 64, 100, 128}, n log-uniform in
+    [1e3, 1e5], half three-view (documents) and half one-view (graphs), 8
+    restarts each; the tile layouts come from the autotuner (run first, timed
+    separately).  The launch sequence is captured into a graph once and the
+    replays are timed (HIP events on the replay stream).  real_rows: the
+    benchmark graph's whitened FP32 rows, for the equal-work check (one k = 100
+    one-view job on them and on planted rows of the same shape)."""
     import tempfile
 
-    import numpy as np
     import torch
     from paper_1309_0787_amd import otm
     import synth
@@ -223,12 +226,13 @@ def bench_batched(steps: int, warmup: int) -> dict:
         ldy = otm.default_ldy(k)
         YA, YB, YC, _ = synth.planted_views(n, k, sp["alpha0"], sp["views"], sub=i, device=dev, ldy=ldy)
         ybar = torch.stack([YA[:, :k].mean(0), YB[:, :k].mean(0), YC[:, :k].mean(0)]).contiguous()
-        Phi0 = torch.as_tensor(np.ascontiguousarray(np.stack([synth.initial_factors(k, restart=r + 100 * i).T for r in range(w["restarts"])])),
+        Phi0 = torch.as_tensor(np.ascontiguousarray(np.stack([synth.initial_factors(k, restart=r + 100 * i).T
+                                                               for r in range(w["restarts"])])),
                                dtype=torch.float32, device=dev)
         g = torch.Generator(device=dev)
         g.manual_seed(1000 + i)
         perms = torch.argsort(torch.rand((w["passes"], n), device=dev, generator=g), dim=1).to(torch.int32)
-        problems.append(otm.Problem(YA, YB, YC, ybar, Phi0, k, sp["alpha0"], perms))   # perms shared by the restarts
+        problems.append(otm.Problem(YA, YB, YC, ybar, Phi0, k, sp["alpha0"], perms))
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     p = otm.SgdParams(k=1, batch=w["batch"], passes=w["passes"], y_dtype=otm.F32, beta0=w["beta0"],
@@ -241,15 +245,17 @@ def bench_batched(steps: int, warmup: int) -> dict:
         t_tune = time.perf_counter() - t0
         tuned = open(cache).read().splitlines()[1:]
         run = otm.BatchedRun(problems, w["restarts"], p, tune_cache=cache)
+    s = torch.cuda.Stream()
+    run.capture(s)
     for _ in range(warmup):
-        run.run()
-    torch.cuda.synchronize()
+        run.replay(s)
+    s.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
+    ev0.record(s)
     for _ in range(steps):
-        run.run()
-    ev1.record()
-    torch.cuda.synchronize()
+        run.replay(s)
+    ev1.record(s)
+    s.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     samples = sum(sp["n"] for sp in table) * w["passes"] * w["restarts"]
     flops = 0.0
@@ -260,9 +266,10 @@ def bench_batched(steps: int, warmup: int) -> dict:
             per_pass += 6.0 * rem * sp["k"] ** 2 + 4.0 * sp["k"] ** 3
         flops += per_pass * (w["passes"] + 1) * w["restarts"]     # training passes + the scoring pass
     achieved = flops / (ms * 1e-3)
-    return {
+    out = {
         "workload": f"{w['problems']} problems, k in {list(w['ks'])}, n log-uniform [{int(w['n_lo'])}, {int(w['n_hi'])}], "
-                    f"half three-view / half one-view, {w['restarts']} restarts, {w['passes']} passes, FP32",
+                    f"half three-view / half one-view, {w['restarts']} restarts, {w['passes']} passes, FP32, "
+                    f"captured launch sequence replayed",
         "samples_per_s": samples / (ms * 1e-3), "ms_per_run": ms, "jobs": len(problems) * w["restarts"],
         "kernel_groups": run.groups,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
@@ -270,6 +277,43 @@ def bench_batched(steps: int, warmup: int) -> dict:
         "nonfinite": int(run.nonfinite.item()), "generation_s": round(t_gen, 2), "autotune_s": round(t_tune, 2),
         "tuned_layouts": tuned,
     }
+    run.close()
+    if real_rows is not None:
+        out["equal_work_check"] = _equal_work_check(real_rows)
+    return out
+
+
+def _equal_work_check(Yreal) -> dict:
+    """One k = 100 one-view job (the benchmark graph's whitened rows, FP32,
+    10 passes) against planted rows of the same shape: microseconds per step."""
+    import torch
+    from paper_1309_0787_amd import otm
+    import synth
+    dev = Yreal.device
+    n, ldy = Yreal.shape
+    k = 100
+    res = {}
+    for name in ("whitened_graph_rows", "planted_rows"):
+        if name == "planted_rows":
+            Y, _, _, _ = synth.planted_views(n, k, 0.5, 1, sub=7, device=dev, ldy=ldy)
+        else:
+            Y = Yreal
+        ybar = torch.stack([Y[:, :k].mean(0)] * 3).contiguous()
+        Phi0 = torch.as_tensor(synth.initial_factors(k, restart=3).T.copy(), dtype=torch.float32, device=dev)[None]
+        pr = [otm.Problem(Y, Y, Y, ybar, Phi0.contiguous(), k, 0.5, None)]
+        p = otm.SgdParams(k=1, batch=100, passes=10, y_dtype=otm.F32, beta0=3e-4, beta_tau=2500.0)
+        run = otm.BatchedRun(pr, 1, p)
+        run.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run.run()
+        e1.record()
+        torch.cuda.synchronize()
+        steps = 11 * ((n + 99) // 100)       # 10 passes and the scoring pass
+        res[name] = {"us_per_step": e0.elapsed_time(e1) * 1e3 / steps, "nonfinite": int(run.nonfinite.item())}
+        run.close()
+    return res
 
 
 WARM = dict(instances=50000, exact_share=0.8, sampled_n=2000, epochs=6, batch=256, lr=1e-3, heldout=1000)
@@ -303,7 +347,9 @@ def train_warm_start(inst, pool_res, w) -> tuple:
         else:
             specs.append(dict(kind="sampled", seed=5000 + i, n=cfg["sampled_n"]))
     t0 = time.perf_counter()
-    tr = pws.build_generated(specs, dev, sampled_pool=pool)
+    tr = pws.build_generated(specs, dev, sampled_pool=pool,
+                             progress=lambda i: print(f"bench: warm start, {i} instances built", file=sys.stderr,
+                                                      flush=True))
     warm = pws.WarmStart(dev, seed=3)
     _, _, X, tgt, _ = warm.prepare(tr)
     torch.cuda.synchronize()
@@ -334,7 +380,8 @@ def bench_heldout(warm) -> dict:
     fams = list(pws.FAMILIES)
     g = np.random.default_rng(1)
     specs = [dict(kind="exact", family=fams[int(g.integers(3))], seed=900000 + i) for i in range(cnt)]
-    hs = pws.build_generated(specs, dev)
+    hs = pws.build_generated(specs, dev, progress=lambda i: print(f"bench: held-out, {i} instances built",
+                                                                  file=sys.stderr, flush=True))
     Pw = pws.warm_factors_batch(warm, hs)
     ks = hs.ks.cpu().numpy()
     rows, tnorm = [], []
@@ -375,6 +422,8 @@ def bench_heldout(warm) -> dict:
             done[newly] = steps
             phis = [ph.clone() for ph in run.Phi]
             run.close()
+            print(f"bench: held-out {arm}, {steps} steps, {int((done > 0).sum())} reached 1e-3", file=sys.stderr,
+                  flush=True)
         ok = done > 0
         out[arm] = {"success_rate": float(ok.mean()),
                     "median_steps_to_1e-3": float(np.median(done[ok])) if ok.any() else None,
@@ -391,11 +440,13 @@ def bench_time_to_loss(inst, C, CT, S, Phi_init, w, warm, warm_info) -> dict:
     {FP32, BF16} x {random: best of 8 random restarts in one launch; warm: the
     learned warm start as restart 0 beside 7 random restarts}, 100 passes
     each.  R of every restart at every pass end from snapshots (outside the
-    timed stages), all against the FP32 arm's tensor.  Threshold: the best
-    converged R over the arms plus 1e-3; an arm's time to loss is its
-    prefix (sketch, whitener, whitening, warm start) plus its STGD time up to
-    the first pass whose best restart reaches the threshold.  Memberships of
-    each arm's best restart against the planted ones."""
+    timed stages), all against the FP32 arm's tensor.  Two thresholds: the
+    best converged R over the arms plus 1e-3 (an arm stuck in a worse basin
+    never reaches it: null), and the worst arm's converged R plus 1e-3, which
+    every arm reaches.  An arm's time to a threshold is its prefix (sketch,
+    whitener, whitening, warm start) plus its STGD time up to the first pass
+    whose best restart reaches it.  Memberships of each arm's best restart
+    against the planted ones."""
     import torch
     from paper_1309_0787_amd import otm, pipeline
     import synth
@@ -422,26 +473,35 @@ def bench_time_to_loss(inst, C, CT, S, Phi_init, w, warm, warm_info) -> dict:
         best_r = int(np.argmin(Rs[:, -1]))
         Pi = otm.recover_pi(res.Y[0], k, res.Phi[best_r], tau=w["tau_pi"])
         runs[name] = dict(stages=tm.spans_ms(), Rs=Rs, best=best_r, rec=recovery_error(Pi, pi_true))
-    r_inf = min(float(r["Rs"][:, -1].min()) for r in runs.values())
+    finals = [float(r["Rs"][:, -1].min()) for r in runs.values()]
+    r_inf = min(finals)
     thr = r_inf + 1e-3
-    out = {"threshold": thr, "R_inf": r_inf, "passes": passes, "restarts": R}
+    thr_common = max(finals) + 1e-3
+    out = {"threshold": thr, "R_inf": r_inf, "threshold_common": thr_common, "passes": passes, "restarts": R}
+
+    def first_pass(best_by_pass, t):
+        hit = np.nonzero(best_by_pass <= t)[0]
+        return int(hit[0]) + 1 if hit.size else None
+
     for name, r in runs.items():
         best_by_pass = r["Rs"].min(axis=0)
-        hit = np.nonzero(best_by_pass <= thr)[0]
-        pz = int(hit[0]) + 1 if hit.size else None
+        pz, pc = first_pass(best_by_pass, thr), first_pass(best_by_pass, thr_common)
         st = r["stages"]
         prefix = st.get("sketch", 0) + st.get("whitener", 0) + st.get("whiten", 0) + st.get("warm", 0)
         out[name] = {"time_to_loss_ms": (prefix + st["stgd"] * pz / passes) if pz else None,
-                     "passes_to_loss": pz, "R_final_best": float(r["Rs"][:, -1].min()),
+                     "passes_to_loss": pz,
+                     "time_to_common_ms": (prefix + st["stgd"] * pc / passes) if pc else None,
+                     "passes_to_common": pc, "R_final_best": float(r["Rs"][:, -1].min()),
                      "R_pass1_best": float(r["Rs"][:, 0].min()), "R_final_warm_restart": float(r["Rs"][0, -1]),
                      "best_restart": r["best"], "stgd_ms": round(st["stgd"], 2), "prefix_ms": round(prefix, 2),
                      "recovery_error": r["rec"]}
-    def ratio(a, b):
-        x, y = out[a]["time_to_loss_ms"], out[b]["time_to_loss_ms"]
+    def ratio(a, b, key):
+        x, y = out[a][key], out[b][key]
         return (x / y) if (x and y) else None
-    out["speedup_warm_fp32"] = ratio("fp32_random", "fp32_warm")
-    out["speedup_warm_bf16"] = ratio("bf16_random", "bf16_warm")
-    out["speedup_bf16_warm_vs_fp32_random"] = ratio("fp32_random", "bf16_warm")
+    for key, tag in (("time_to_loss_ms", ""), ("time_to_common_ms", "_common")):
+        out["speedup_warm_fp32" + tag] = ratio("fp32_random", "fp32_warm", key)
+        out["speedup_warm_bf16" + tag] = ratio("bf16_random", "bf16_warm", key)
+        out["speedup_bf16_warm_vs_fp32_random" + tag] = ratio("fp32_random", "bf16_warm", key)
     out["warm_start"] = warm_info
     return out
 
@@ -501,75 +561,6 @@ def recovery_error(Pi: "torch.Tensor", pi_true: "np.ndarray") -> float:
     M = np.zeros_like(T)
     M[c] = P[r]
     return float(np.linalg.norm(M - T) / np.linalg.norm(T))
-
-
-def bench_time_to_loss(inst, C, CT, S, perms, Phi_init, w) -> dict:
-    """Time to the converged loss: FP32 path from random factors against the
-    BF16 path from the learned warm start, on the benchmark graph.  R(Phi) is
-    evaluated at every pass end from snapshots, outside the timed stages; the
-    threshold is the FP32 path's final R plus 1e-3.  The warm start is trained
-    first (timed separately) on exact-moment instances (k in {10, 50, 100}) and
-    planted-mixture rows."""
-    import numpy as np
-    import torch
-    from paper_1309_0787_amd import otm, pipeline
-    from paper_1309_0787_amd import warmstart as pws
-
-    dev = torch.device("cuda:0")
-    ws_cfg = WARM
-    g = np.random.default_rng(0)
-    specs = []
-    for i in range(ws_cfg["instances"]):
-        if g.random() < ws_cfg["exact_share"]:
-            specs.append(dict(k=int(g.choice([10, 50, 100, 100, 100])), seed=5000 + i, kind="exact"))
-        else:
-            specs.append(dict(k=w["k"], seed=5000 + i, kind="sampled", n=ws_cfg["sampled_n"], alpha0=w["alpha0"],
-                              views=1))
-    t0 = time.perf_counter()
-    tr = pws.build_instances(specs, dev)
-    warm = pws.WarmStart(dev, seed=3)
-    _, _, X, tgt, _ = warm.prepare(tr)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    losses = warm.train(X, tgt, tr.ks, epochs=ws_cfg["epochs"], batch=ws_cfg["batch"], lr=ws_cfg["lr"])
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    del X, tgt, tr
-    k = w["k"]
-    runs = {}
-    pi_true = inst.pi[inst.X]
-    for name, ydt, use_warm in (("fp32_random", otm.F32, False), ("bf16_warm", otm.BF16, True)):
-        cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=ydt,
-                                 batch=w["batch"], passes=w["passes"], beta0=w["beta0"], beta_tau=w["beta_tau"],
-                                 tau_pi=w["tau_pi"])
-        Phi = Phi_init.clone()
-        tm = pipeline.Timer(True)
-        res = pipeline.fit([C], C, CT, S, Phi, perms, cfg, pi_view=0, snapshots=True, timer=tm,
-                           warm=warm if use_warm else None)
-        torch.cuda.synchronize()
-        spans = tm.spans_ms()
-        T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
-        Rs = otm.residual(T, res.snapshots[0].contiguous()).cpu().numpy()
-        runs[name] = dict(stages_ms={a: round(b, 3) for a, b in spans.items()}, R_by_pass=[float(x) for x in Rs],
-                          recovery_error=recovery_error(res.Pi, pi_true))
-    r_inf = runs["fp32_random"]["R_by_pass"][-1]
-    thr = r_inf + 1e-3
-    out = {"threshold": thr, "R_inf_fp32": r_inf}
-    for name, r in runs.items():
-        hit = [i for i, x in enumerate(r["R_by_pass"]) if x <= thr]
-        passes = hit[0] + 1 if hit else None
-        st = r["stages_ms"]
-        prefix = st.get("sketch", 0) + st.get("whitener", 0) + st.get("whiten", 0) + st.get("warm", 0)
-        ttl = prefix + st["stgd"] * passes / w["passes"] if passes else None
-        out[name] = {"time_to_loss_ms": ttl, "passes_to_loss": passes, "R_final": r["R_by_pass"][-1],
-                     "R_pass1": r["R_by_pass"][0], "stgd_ms_50_passes": st["stgd"], "prefix_ms": prefix,
-                     "warm_ms": st.get("warm"), "recovery_error": r["recovery_error"]}
-    a, b = out["fp32_random"]["time_to_loss_ms"], out["bf16_warm"]["time_to_loss_ms"]
-    out["speedup"] = (a / b) if (a and b) else None
-    out["warm_start"] = {"train_instances": ws_cfg["instances"], "epochs": ws_cfg["epochs"],
-                         "build_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
-                         "final_loss": float(np.mean(losses[-10:])), "adam_steps": len(losses)}
-    return out
 
 
 def _validation_record(Pi_hat, pi_true) -> dict:
@@ -688,6 +679,105 @@ def bench_four_partition(w) -> dict:
     return out
 
 
+def oracle_stage_timing(inst, w) -> dict:
+    """The FP64 oracle per stage on the benchmark graph (one M2 application
+    to the 2k-column sketch, the whitener, the whitening, 200 STGD steps, the
+    memberships), median of 5 runs after one warm-up, with the linear algebra
+    libraries held to one thread and then to all of the host's cores."""
+    import platform
+    import statistics
+
+    import oracle
+    import synth
+    from threadpoolctl import threadpool_info, threadpool_limits
+    k, a0 = w["k"], w["alpha0"]
+    C = inst.C
+    S = synth.projection(C.n_cols, 2 * k, seed=1)
+    O = oracle.m2_apply(C, S, a0, False)
+    Q, O = oracle.power_sketch(C, S, a0, False, 1)
+    W, _ = oracle.whitener_rsvd(O, Q, k)
+    Y, yb = oracle.whiten(C, W, False)
+    yb3 = np.stack([yb] * 3)
+    steps = 200
+    spp = (C.n_rows + w["batch"] - 1) // w["batch"]
+    perms = synth.permutations(C.n_rows, (steps + spp - 1) // spp, seed=2)
+    Phi0 = synth.initial_factors(k, seed=4)
+    stages = {
+        "m2_apply": lambda: oracle.m2_apply(C, S, a0, False),
+        "whitener": lambda: oracle.whitener_rsvd(O, Q, k),
+        "whiten": lambda: oracle.whiten(C, W, False),
+        "stgd_200_steps": lambda: oracle.sgd_run(Y, Y, Y, yb3, Phi0, perms, w["batch"], w["beta0"], w["beta_tau"], a0,
+                                                 end_step=steps),
+        "memberships": lambda: oracle.recover_pi(Y, Phi0, w["tau_pi"]),
+    }
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    model = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+           "blas_threads_all": int(cores), "runs": "median of 5 after 1 warm-up"}
+    for label, limit in (("1_thread", 1), ("all_cores", int(cores))):
+        rec = {}
+        with threadpool_limits(limits=limit):
+            for name, fn in stages.items():
+                fn()
+                ts = []
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    fn()
+                    ts.append(time.perf_counter() - t0)
+                rec[name + "_ms"] = round(statistics.median(ts) * 1e3, 3)
+        rec["stgd_samples_per_s"] = steps * w["batch"] / (rec["stgd_200_steps_ms"] * 1e-3)
+        out[label] = rec
+    return out
+
+
+def bench_peaks() -> dict:
+    """The device's own rates measured by the library's probes: a 16-byte
+    vector copy of 4 GiB (HBM read + write bytes over the time; best of 5)
+    and whole-device matrix-core chains in BF16, FP32 and FP64 (best of 3)."""
+    import torch
+    from paper_1309_0787_amd import otm
+    dev = torch.device("cuda:0")
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    blocks = 256 * 16
+    otm.probe_copy(src, dst, blocks)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        otm.probe_copy(src, dst, blocks)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    out = {"hbm_copy_gb_s": 2.0 * nbytes / (best * 1e-3) / 1e9, "copy_bytes": nbytes}
+    del src, dst
+    sink = torch.empty(256 * 8 * 256, dtype=torch.float32, device=dev)
+    for name, dt, iters in (("bf16", otm.BF16, 4000), ("fp32", otm.F32, 4000), ("fp64", otm.F64, 2000)):
+        blocks = 256 * 8
+        otm.probe_mfma(dt, 100, blocks, sink)
+        best = float("inf")
+        flops = 0
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            flops = otm.probe_mfma(dt, iters, blocks, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[f"mfma_{name}_tflop_s"] = flops / (best * 1e-3) / 1e12
+    out["datasheet"] = {"hbm_gb_s": 8000.0, "mfma_bf16_tflop_s": 2500.0, "mfma_fp32_tflop_s": 157.3,
+                        "mfma_fp64_tflop_s": 78.6}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -698,6 +788,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-problem measurement")
     ap.add_argument("--no-time-to-loss", action="store_true", help="skip the warm-start time-to-loss measurement")
     ap.add_argument("--no-spmm", action="store_true", help="skip the document whitening SpMM measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip validation, four-partition, measured peaks and per-stage oracle timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (scale for the HBM counters)")
     ap.add_argument("--print-kernel-hash", action="store_true", help="print the STGD kernel source hash and exit")
@@ -792,11 +884,17 @@ def main():
         "sgd_us_per_step": sgd_ms * 1e3 / (w["passes"] * ((n + w["batch"] - 1) // w["batch"])),
         "generation_s": round(t_gen, 2),
     }
-    print("bench: validation (recovery ratio, error) and the four-partition estimator", file=sys.stderr, flush=True)
-    out["validation"] = {"large": dict(_validation_record(res.Pi, inst.pi[inst.X]),
-                                       recovery_error=recovery_error(res.Pi, inst.pi[inst.X])),
-                         "small": bench_validation_small()}
-    out["four_partition"] = bench_four_partition(w)
+    if not args.no_extras:
+        print("bench: measured peaks", file=sys.stderr, flush=True)
+        out["measured_peaks"] = bench_peaks()
+        pk = out["measured_peaks"]
+        out["roofline"]["frac_measured_peak"] = achieved / (pk["mfma_bf16_tflop_s"] * 1e12)
+        print("bench: validation (recovery ratio, error)", file=sys.stderr, flush=True)
+        out["validation"] = {"large": dict(_validation_record(res.Pi, inst.pi[inst.X]),
+                                           recovery_error=recovery_error(res.Pi, inst.pi[inst.X])),
+                             "small": bench_validation_small()}
+        print("bench: four-partition estimator", file=sys.stderr, flush=True)
+        out["four_partition"] = bench_four_partition(w)
     if args.quality:
         T = otm.tensor_form(res.Y[0], res.Y[1], res.Y[2], k, res.ybar3, w["alpha0"])
         out["quality"] = {"residual": float(otm.residual(T, res.Phi[0]).item()),
@@ -818,7 +916,8 @@ def main():
         out["spmm"] = bench_spmm(docs)
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
-        out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1)
+        Yr = res.Y[0].float().contiguous() if res.Y[0].dtype != torch.float32 else res.Y[0]
+        out["batched"] = bench_batched(max(1, min(args.steps, 3)), 1, real_rows=Yr)
     if not args.no_cpu_baseline:
         print("bench: oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"], ores = cpu_baseline(inst, w)
@@ -826,6 +925,9 @@ def main():
         out["error_vs_oracle"] = {"graph": errors_graph(res, ores, w, inst)}
         print("bench: per-result errors against the oracle (documents)", file=sys.stderr, flush=True)
         out["error_vs_oracle"]["documents"] = errors_documents(docs)
+        if not args.no_extras:
+            print("bench: oracle per stage, one thread and all cores", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["per_stage"] = oracle_stage_timing(inst, w)
     print(json.dumps(out), flush=True)
 
 

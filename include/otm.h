@@ -537,6 +537,19 @@ size_t otm_residual_workspace(int32_t k, int32_t count);
 int otm_residual(const double* T, int32_t k, const float* Phi, int32_t count, double* R,
                  void* ws, size_t ws_bytes, otm_stream stream);
 
+/* ---- measurement probes: the device's own rates, beside the datasheet
+ * figures the roofline fractions use ------------------------------------------
+ * otm_probe_copy: dst = src over `bytes` (a positive multiple of 16, both
+ * 16-byte aligned, not overlapping) with 16-byte vectors on `blocks`
+ * workgroups of 256 threads, grid-stride: HBM bandwidth = 2 bytes / time.
+ * otm_probe_mfma: every wave of `blocks` workgroups (four waves each) runs
+ * `iters` rounds of eight independent matrix-core chains of dtype OTM_BF16
+ * (16x16x32), OTM_F32 or OTM_F64 (16x16x4); out: blocks x 256 floats (sums that
+ * keep the work alive).  otm_probe_mfma_flops gives the flops of such a launch. */
+int otm_probe_copy(const void* src, void* dst, int64_t bytes, int32_t blocks, otm_stream stream);
+int64_t otm_probe_mfma_flops(int dtype, int64_t iters, int32_t blocks);
+int otm_probe_mfma(int dtype, int64_t iters, int32_t blocks, float* out, otm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

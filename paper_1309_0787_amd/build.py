@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libotm.so")
-SOURCES = ["api.hip", "spmm.hip", "stgd.hip", "batched.hip", "warmstart.hip", "dense64.hip", "jacobi.hip", "post.hip", "community.hip", "validation.hip"]
+SOURCES = ["api.hip", "spmm.hip", "stgd.hip", "batched.hip", "warmstart.hip", "dense64.hip", "jacobi.hip", "post.hip", "community.hip", "validation.hip", "probe.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

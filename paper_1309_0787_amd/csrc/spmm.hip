@@ -71,7 +71,7 @@ __device__ __forceinline__ void clamp_row(const int32_t* rowptr, int64_t nnz, in
 template <int VPL, int LPR, class TW, class TY, int NT = kSpmmThreads, bool LDSW = false>
 __global__ __launch_bounds__(NT) void whiten_kernel(otm_csr C, int normalize, const TW* __restrict__ W,
                                                    int k, int ldw, TY* __restrict__ Y, int ldy,
-                                                   float* __restrict__ part) {
+                                                   float* __restrict__ part, int yfull) {
     constexpr int lpr = LPR;
     constexpr int rows_per_block = NT / LPR;
     __shared__ float s_colsum[rows_per_block * LPR * VPL];
@@ -164,7 +164,22 @@ __global__ __launch_bounds__(NT) void whiten_kernel(otm_csr C, int normalize, co
             }
             const float r = normalize ? (rowsum > 0.f ? 1.0f / rowsum : 0.f) : 1.0f;
             TY* yrow = Y + (size_t)row * ldy;
-            if (active) {
+            if (yfull) {
+                // whole rows in one vector store per lane, the padding
+                // columns' zeros included: a wave's rows leave as whole lines
+                typedef TY YVec __attribute__((ext_vector_type(VPL)));
+                if (col0 < ldy) {
+                    YVec y;
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) {
+                        const bool live_c = col0 + v < k;
+                        const float yv = live_c ? acc[v] * r : 0.0f;
+                        if (live_c) colacc[v] += yv;
+                        y[v] = static_cast<TY>(yv);
+                    }
+                    __builtin_nontemporal_store(y, reinterpret_cast<YVec*>(yrow + col0));
+                }
+            } else if (active) {
                 typedef TY YVec __attribute__((ext_vector_type(VPL)));
                 TY* dst = yrow + col0;
                 if (col0 + VPL <= k && reinterpret_cast<uintptr_t>(dst) % sizeof(YVec) == 0) {
@@ -187,7 +202,8 @@ __global__ __launch_bounds__(NT) void whiten_kernel(otm_csr C, int normalize, co
                     }
                 }
             }
-            for (int c = k + g_lane; c < ldy; c += lpr) __builtin_nontemporal_store(static_cast<TY>(0.0f), yrow + c);
+            if (!yfull)
+                for (int c = k + g_lane; c < ldy; c += lpr) __builtin_nontemporal_store(static_cast<TY>(0.0f), yrow + c);
         }
     }
     // block column sums in a fixed order: slots 0..rows_per_block-1
@@ -231,11 +247,21 @@ __global__ __launch_bounds__(kFinThreads) void colsum_finalize_kernel(const floa
     if (threadIdx.x == 0) out[c] = static_cast<float>(red[0] * scale);
 }
 
+// Whole-row vector stores of Y: every lane's vector inside the row stride and
+// aligned (ldy a multiple of the vector, Y aligned to it), and the row's
+// lanes covering the whole stride.
+template <int VPL, int LPR, class TY>
+int y_full_rows(const void* Y, int ldy) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(Y);
+    return (ldy % VPL == 0 && a % (VPL * sizeof(TY)) == 0 && LPR * VPL >= ldy) ? 1 : 0;
+}
+
 template <int VPL, int LPR, class TW, class TY>
 int launch_whiten(const otm_csr& C, int normalize, const void* W, int k, int ldw, void* Y, int ldy, float* part,
                   int nblocks, hipStream_t st) {
     hipLaunchKernelGGL((whiten_kernel<VPL, LPR, TW, TY>), dim3(nblocks), dim3(kSpmmThreads), 0, st, C, normalize,
-                       static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part);
+                       static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part,
+                       y_full_rows<VPL, LPR, TY>(Y, ldy));
     return check_launch("whiten_kernel");
 }
 
@@ -262,7 +288,8 @@ int launch_whiten_lds(const otm_csr& C, int normalize, const void* W, int k, int
     const int ks = (k + VPL - 1) / VPL * VPL;
     const size_t shm = sizeof(TW) * (size_t)C.n_cols * ks;
     hipLaunchKernelGGL((whiten_kernel<VPL, LPR, TW, TY, kLdsWThreads, true>), dim3(nblocks), dim3(kLdsWThreads), shm,
-                       st, C, normalize, static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part);
+                       st, C, normalize, static_cast<const TW*>(W), k, ldw, static_cast<TY*>(Y), ldy, part,
+                       y_full_rows<VPL, LPR, TY>(Y, ldy));
     return check_launch("whiten_kernel (W in LDS)");
 }
 

@@ -146,6 +146,9 @@ _SIGS = {
     "otm_validate_workspace": (_sz, [_i32, _i32, _i32]),
     "otm_validate": (ctypes.c_int, [_vp, _i32, _vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "otm_bridgeness": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_CSR), _vp, _vp, _vp]),
+    "otm_probe_copy": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp]),
+    "otm_probe_mfma_flops": (_i64, [ctypes.c_int, _i64, _i32]),
+    "otm_probe_mfma": (ctypes.c_int, [ctypes.c_int, _i64, _i32, _vp, _vp]),
     "otm_tensor_form": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _i32, _i32, _i32, _vp, _dbl, _vp, _vp]),
     "otm_residual_workspace": (_sz, [_i32, _i32]),
     "otm_residual": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
@@ -779,6 +782,17 @@ def bridgeness(Pi_hat: torch.Tensor, G: DeviceCSR | None = None, stream=None):
     _check(lib().otm_bridgeness(_ptr(Pi_hat), kh, n, ctypes.byref(gc) if gc is not None else None, _ptr(b), _ptr(bd),
                                 _stream(stream)))
     return b, bd
+
+
+# ------------------------------------------------------------------ measurement probes
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, blocks: int, stream=None):
+    _check(lib().otm_probe_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), int(blocks), _stream(stream)))
+
+
+def probe_mfma(dtype: int, iters: int, blocks: int, out: torch.Tensor, stream=None) -> int:
+    """Launches the matrix-core probe; returns its flops."""
+    _check(lib().otm_probe_mfma(int(dtype), int(iters), int(blocks), _ptr(out), _stream(stream)))
+    return int(lib().otm_probe_mfma_flops(int(dtype), int(iters), int(blocks)))
 
 
 # ------------------------------------------------------------------ loss

@@ -171,17 +171,18 @@ FAMILIES = {
 
 
 def family_weights(family: str, seed: int) -> np.ndarray:
-    """Community shares of a workload's samples as its generator draws them:
-    memberships pi ~ Dir(alpha0/k 1) for its n samples (Section 2), each
-    sample taken in its largest community (the block-model limit, which keeps
-    the whitened third moment exactly orthogonal); returns alpha_hat_j, the
-    share of community j (empty communities get one sample)."""
+    """Community shares of a workload's samples as its generator draws them,
+    at the block-model limit (each sample in its largest community, which
+    keeps the whitened third moment exactly orthogonal): the memberships are
+    pi ~ Dir(alpha0/k 1) (Section 2), a symmetric law, so the index of the
+    largest entry is uniform over the k communities and the counts of the n
+    samples are Multinomial(n, 1/k) (drawn directly).  Returns alpha_hat_j,
+    the share of community j (an empty community gets one sample)."""
     import synth
     f = FAMILIES[family]
     k, n = f["k"], f["n"]
     g = synth.rng(seed, synth.S_MISC, 31)
-    pi = g.dirichlet(np.full(k, f["alpha0"] / k), size=n)
-    counts = np.bincount(np.argmax(pi, axis=1), minlength=k).astype(np.float64)
+    counts = g.multinomial(n, np.full(k, 1.0 / k)).astype(np.float64)
     counts = np.maximum(counts, 1.0)
     return counts / counts.sum()
 
@@ -201,12 +202,13 @@ def generated_exact_instance(family: str, seed: int):
     return Y, U, lam
 
 
-def build_generated(specs: list[dict], device, sampled_pool=None, P: int | None = None) -> InstanceSet:
+def build_generated(specs: list[dict], device, sampled_pool=None, P: int | None = None, progress=None) -> InstanceSet:
     """specs: dicts with family and seed, kind 'exact' (generated_exact_instance)
     or 'sampled': rows[i] of a whitened sample pool (sampled_pool: dict with Y
     (n x ldy FP32, device), U (k x k planted directions in the whitened
     coordinates), lam (k), alpha0) restricted to a seeded subset of size
-    spec['n'].  Sketches run on the GPU."""
+    spec['n'].  Sketches run on the GPU.  progress: None or a callable
+    taking the number of instances built (called every 5000)."""
     P = P or otm.ws_dims()["P"]
     cnt = len(specs)
     ks = torch.zeros(cnt, dtype=torch.int32, device=device)
@@ -235,6 +237,8 @@ def build_generated(specs: list[dict], device, sampled_pool=None, P: int | None 
         otm.ws_sketch(YA, YB, YC, k, ybar, a0, th[:k].contiguous(), S[i])
         U[i, :k, :k] = torch.as_tensor(np.asarray(Ui), dtype=torch.float32, device=device)
         lam[i, :k] = torch.as_tensor(np.asarray(li), dtype=torch.float32, device=device)
+        if progress is not None and (i + 1) % 5000 == 0:
+            progress(i + 1)
     ks.copy_(torch.tensor(kk, dtype=torch.int32))
     return InstanceSet(ks, S, Th, U, lam)
 
