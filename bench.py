@@ -6,7 +6,8 @@ k = 100 communities, alpha0 = 0.5, p = 0.05, q = 0.001, seeded synthetic.
 One step = the whole path on one batch of input already resident in HBM:
 power-iterated M2 sketch (FP64) -> randomized whitener (FP64) -> whitening
 SpMM (BF16 W and Y, FP32 accumulation) -> STGD run (50 passes, mini-batch 100,
-BF16 matrix-core contractions, FP32 compensated update) -> memberships (FP64).
+BF16 matrix-core contractions, FP32 master with the plain update) -> memberships
+(FP64).
 
 value = whitened samples pushed through STGD per second of a whole step
 (n_X * passes / step time).  Prints one JSON line.
@@ -27,12 +28,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOAD = dict(name="mmsb_large", n=100000, n_x=50000, k=100, alpha0=0.5, p=0.05, q=0.001, batch=100, passes=50,
-                q_power=3, beta0=1e-3, beta_tau=2500.0, tau_pi=0.1)
+                q_power=3, beta0=1e-3, beta_tau=2500.0, tau_pi=0.1, compensated=False)
 PEAK_BF16 = 2.5e15          # dense MFMA bf16, FLOP/s
 PEAK_HBM = 8.0e12           # bytes/s
 # HBM counters of the STGD kernel (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE), per launch,
 # valid only for the kernel source they were taken on.
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sgd_kernel_mmsb_large_counters.json")
+WHITEN_COUNTERS_FILE = os.path.join(ROOT, "profiles", "whiten_kernel_counters.json")
 
 
 def sgd_flops(n: int, batch: int, k: int, passes: int) -> float:
@@ -45,12 +47,12 @@ def sgd_flops(n: int, batch: int, k: int, passes: int) -> float:
     return per_pass * passes
 
 
-def kernel_hash() -> str:
-    """Hash of the STGD kernel's sources without comments and blank lines (the
-    counters are valid for this code only)."""
+def kernel_hash(files=("stgd.hip", "stgd_kernel.h")) -> str:
+    """Hash of a kernel's sources without comments and blank lines (the
+    counters are valid for this code only); by default the STGD kernel's."""
     import re
     h = hashlib.sha256()
-    for f in ("stgd.hip", "stgd_kernel.h"):
+    for f in files:
         src = open(os.path.join(ROOT, "paper_1309_0787_amd", "csrc", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
@@ -66,6 +68,19 @@ def counters_traffic():
     if c.get("kernel_sha256_16") != kernel_hash():
         return None
     return c.get("bytes_per_launch")
+
+
+def whiten_traffic(workload: str):
+    """HBM bytes per launch of the whitening SpMM on `workload` ("documents":
+    one view; "graph": the benchmark graph's block) from the committed
+    counters, or None when spmm.hip has changed since they were taken."""
+    try:
+        c = json.load(open(WHITEN_COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_sha256_16") != kernel_hash(("spmm.hip",)):
+        return None
+    return c.get("workloads", {}).get(workload, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(inst, w):
@@ -125,13 +140,28 @@ def errors_graph(res, ores, w, inst=None) -> dict:
            "Phi": _rel(_host(res.Phi[0]).T, ores["Phi"]),
            "Pi": _rel(Pi_g, ores["Pi"]), "Pi_max_abs": float(np.abs(Pi_g - ores["Pi"]).max()),
            "precision": "W FP64 (BF16 copy for the SpMM), Y BF16, STGD BF16 operands / FP32 accumulate and "
-                        "compensated FP32 master, Pi FP64 arithmetic; Y and Phi include the BF16 rounding"}
+                        "plain FP32 master, Pi FP64 arithmetic; Y and Phi include the BF16 rounding"}
     dev = res.W.device
+    permd = torch.as_tensor(ores["perms"], device=dev)
+    # the same BF16 run with the compensated master update, on the step's own
+    # BF16 rows: factor error and microseconds per step beside the plain one
+    Yb = res.Y[0]
+    ybg = res.ybar3
+    pb = otm.SgdParams(k=k, batch=w["batch"], passes=w["passes"], y_dtype=otm.BF16, compensated=True,
+                       alpha0=w["alpha0"], beta0=w["beta0"], beta_tau=w["beta_tau"], ldy=Yb.shape[1])
+    Phi = torch.as_tensor(ores["Phi0"].T.copy(), dtype=torch.float32, device=dev)[None].contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    otm.sgd_run(pb, n, Yb, Yb, Yb, ybg, permd, Phi)
+    e1.record()
+    torch.cuda.synchronize()
+    steps = w["passes"] * ((n + w["batch"] - 1) // w["batch"])
+    out["Phi_bf16_compensated"] = _rel(_host(Phi[0]).T, ores["Phi"])
+    out["stgd_us_per_step_bf16_compensated"] = e0.elapsed_time(e1) * 1e3 / steps
     ldy = otm.default_ldy(k)
     Y32 = torch.zeros((n, ldy), dtype=torch.float32, device=dev)
     Y32[:, :k] = torch.as_tensor(ores["Y"], dtype=torch.float32, device=dev)
     yb3 = torch.as_tensor(ores["ybar"].astype(np.float32).reshape(-1), device=dev)
-    permd = torch.as_tensor(ores["perms"], device=dev)
     for comp in (True, False):
         p = otm.SgdParams(k=k, batch=w["batch"], passes=w["passes"], y_dtype=otm.F32, compensated=comp,
                           alpha0=w["alpha0"], beta0=w["beta0"], beta_tau=w["beta_tau"], ldy=ldy)
@@ -460,9 +490,11 @@ def bench_time_to_loss(inst, C, CT, S, Phi_init, w, warm, warm_info) -> dict:
     pi_true = inst.pi[inst.X]
     for name, ydt, use_warm in (("fp32_random", otm.F32, False), ("fp32_warm", otm.F32, True),
                                 ("bf16_random", otm.BF16, False), ("bf16_warm", otm.BF16, True)):
+        # FP32 arms with the compensated master update, BF16 arms with the
+        # plain one (as the benchmark step)
         cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=ydt,
                                  batch=w["batch"], passes=passes, beta0=w["beta0"], beta_tau=w["beta_tau"],
-                                 tau_pi=w["tau_pi"], restarts=R)
+                                 tau_pi=w["tau_pi"], restarts=R, compensated=(ydt == otm.F32))
         Phi = Phi_rand.clone()
         tm = pipeline.Timer(True)
         res = pipeline.fit([C], C, CT, S, Phi, perms, cfg, snapshots=True, timer=tm, warm=warm if use_warm else None)
@@ -541,11 +573,50 @@ def bench_spmm(inst, reps: int = 20) -> dict:
     nnz = sum(v.nnz for v in inst.views)
     algo = nnz * 8 + 3 * 4 * (n + 1) + 3 * n * ldy * 4 + d * k * 4
     achieved = algo / (ms * 1e-3)
+    per = whiten_traffic("documents")
+    traffic = 3 * per if per else None
     return {"workload": f"documents d={d}, k={k}, n={n}, three views, nnz={nnz}, FP32",
             "ms_per_three_views": ms, "algorithmic_bytes": algo,
             "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                         "frac": achieved / PEAK_HBM},
+                         "frac": achieved / PEAK_HBM, "traffic": traffic,
+                         "traffic_gb_s": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
+                         "traffic_over_algorithmic": (traffic / algo) if traffic else None},
             "w_gather_bytes": nnz * ldw * 4, "w_gather_tb_per_s": nnz * ldw * 4 / (ms * 1e-3) / 1e12}
+
+
+def bench_whiten_graph(C, W, k: int, reps: int = 20) -> dict:
+    """Whitening SpMM of the benchmark graph's block G[X, A] (BF16 W and Y,
+    no weights), as the step runs it: algorithmic HBM bytes nnz 4 + 4 (n + 1)
+    + d k 2 + n ldy 2 per launch, HIP events over `reps` launches, and the
+    counter traffic when it is current."""
+    import torch
+    from paper_1309_0787_amd import otm
+    n, d = C.n_rows, C.n_cols
+    ldy = otm.default_ldy(k)
+    # the whitener's BF16 copy of W: rows padded to 16 bytes
+    Wbuf = torch.zeros((d, otm.default_ldw(k, otm.BF16)), dtype=torch.bfloat16, device=W.device)
+    Wbuf[:, :k] = W.to(torch.bfloat16)
+    W_lo = Wbuf[:, :k]
+    Y = torch.empty((n, ldy), dtype=torch.bfloat16, device=W.device)
+    otm.whiten(C, False, W_lo, y_dtype=otm.BF16, out=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        otm.whiten(C, False, W_lo, y_dtype=otm.BF16, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    algo = C.nnz * 4 + 4 * (n + 1) + d * k * 2 + n * ldy * 2
+    achieved = algo / (ms * 1e-3)
+    traffic = whiten_traffic("graph")
+    return {"workload": f"graph block G[X, A], {n} x {d}, nnz={C.nnz}, k={k}, BF16 W and Y",
+            "ms_per_launch": ms, "algorithmic_bytes": algo,
+            "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": achieved / PEAK_HBM, "traffic": traffic,
+                         "traffic_gb_s": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
+                         "traffic_over_algorithmic": (traffic / algo) if traffic else None},
+            "w_gather_bytes": C.nnz * otm.default_ldw(k, otm.BF16) * 2}
 
 
 def recovery_error(Pi: "torch.Tensor", pi_true: "np.ndarray") -> float:
@@ -833,7 +904,7 @@ def main():
     Phi = torch.empty_like(Phi_init)
     cfg = pipeline.FitConfig(k=k, alpha0=w["alpha0"], normalize=False, q_power=w["q_power"], y_dtype=otm.BF16,
                              batch=w["batch"], passes=w["passes"], beta0=w["beta0"], beta_tau=w["beta_tau"],
-                             tau_pi=w["tau_pi"])
+                             tau_pi=w["tau_pi"], compensated=w["compensated"])
 
     def step(timer=None):
         Phi.copy_(Phi_init)
@@ -874,10 +945,11 @@ def main():
         "config": {"workload": f"MMSB n={w['n']} (X/A {w['n_x']}/{w['n'] - w['n_x']}) k={k} alpha0={w['alpha0']} "
                                f"p={w['p']} q={w['q']} nnz(G[X,A])={inst.C.nnz}",
                    "batch": w["batch"], "passes": w["passes"], "restarts": 1, "sketch_power_iterations": w["q_power"],
-                   "precision": "BF16 W/Y and STGD contractions, FP32 accumulate and master, FP64 sketch/whitener/post"},
+                   "precision": "BF16 W/Y and STGD contractions, FP32 accumulate and FP32 master (plain update), "
+                                "FP64 sketch/whitener/post"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16, "traffic": counters_traffic(),
-                     "kernel": "sgd_kernel<MmaBF16,128>", "flops_per_launch": flops, "launch_ms": sgd_ms,
+                     "kernel": "sgd_kernel<MmaBF16,128,1,plain>", "flops_per_launch": flops, "launch_ms": sgd_ms,
                      "frac_one_cu": achieved / (PEAK_BF16 / 256)},
         "stage_ms": {kname: round(v, 4) for kname, v in stages.items()},
         "sgd_samples_per_s": n * w["passes"] / (sgd_ms * 1e-3),
@@ -912,8 +984,9 @@ def main():
         docs = synth.make("lda_medium")
         print(f"bench: document workload generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_spmm:
-        print("bench: whitening SpMM on the document workload", file=sys.stderr, flush=True)
+        print("bench: whitening SpMM on the document workload and the graph", file=sys.stderr, flush=True)
         out["spmm"] = bench_spmm(docs)
+        out["spmm_graph"] = bench_whiten_graph(C, res.W, k)
     if not args.no_batched:
         print("bench: batched workload", file=sys.stderr, flush=True)
         Yr = res.Y[0].float().contiguous() if res.Y[0].dtype != torch.float32 else res.Y[0]

@@ -4,25 +4,29 @@
 namespace otm {
 namespace {
 
-template <class M, int KP, int NSTAGE>
+template <class M, int KP, int NSTAGE, bool COMP>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     __shared__ __attribute__((aligned(16))) SgdSmem<M, KP, NSTAGE, 4> sm;
-    sgd_body<M, KP, NSTAGE, 4, false>(g, blockIdx.x, sm);
+    sgd_body<M, KP, NSTAGE, 4, false, COMP>(g, blockIdx.x, sm);
 }
 
-template <class M, int KP, int NSTAGE>
+template <class M, int KP, int NSTAGE, bool COMP>
 int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
     static_assert(smem_bytes<M, KP, NSTAGE>() <= kLdsLimit, "STGD shared memory exceeds 160 KB");
-    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE>), dim3(restarts), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP>), dim3(restarts), dim3(kThreads), 0, st, a);
     return check_launch("sgd_kernel");
 }
 
 // Picks the instantiation: the smallest padded k, then the largest batch
-// staging that fits in LDS (one view when the three views alias).
+// staging that fits in LDS (one view when the three views alias).  BF16 runs
+// without compensation take the variant that keeps no compensation terms
+// (FP32 keeps them: there they also carry -beta kappa O through the step).
 template <class M, int KP>
 int dispatch_staging(const SgdArgs& a, int restarts, bool aliased, hipStream_t st) {
     constexpr int s1 = staging_for<M, KP>(true), s3 = staging_for<M, KP>(false);
-    return aliased ? launch_sgd<M, KP, s1>(a, restarts, st) : launch_sgd<M, KP, s3>(a, restarts, st);
+    if (M::EPL != 1 && !a.compensated)
+        return aliased ? launch_sgd<M, KP, s1, false>(a, restarts, st) : launch_sgd<M, KP, s3, false>(a, restarts, st);
+    return aliased ? launch_sgd<M, KP, s1, true>(a, restarts, st) : launch_sgd<M, KP, s3, true>(a, restarts, st);
 }
 
 int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB, const void* YC,

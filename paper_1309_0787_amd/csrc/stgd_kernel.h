@@ -256,7 +256,7 @@ constexpr int staging_for(bool aliased) {
 }
 
 // One whole run of restart r_id of the problem in g, by the calling workgroup.
-template <class M, int KP, int NSTAGE, int WR, bool SCORE>
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true>
 __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     using Op = typename M::Op;
     using Y = typename M::Y;
@@ -309,9 +309,12 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     // ---- master copy of Phi: tile (mt, nt) holds a = row, i = column.  In
     // BF16 it lives in registers; in FP32 the LDS operand copy is exact, so it
     // is the master copy itself and the registers go to the products.  The
-    // compensation terms stay in registers.
+    // compensation terms stay in registers.  COMP = false (BF16 only, for runs
+    // without compensation) drops them: -beta kappa O then goes straight into
+    // the register master copy, which frees TRK * TC * 4 registers.
     constexpr bool kPhiReg = M::EPL != 1;
-    f32x4 phi_r[kPhiReg ? TRK : 1][kPhiReg ? TC : 1], comp[TRK][TC];
+    constexpr bool kComp = COMP || !kPhiReg;
+    f32x4 phi_r[kPhiReg ? TRK : 1][kPhiReg ? TC : 1], comp[kComp ? TRK : 1][kComp ? TC : 1];
     auto phi_get = [&](int ti, int tj) -> f32x4 {
         if constexpr (kPhiReg) {
             return phi_r[ti][tj];
@@ -339,7 +342,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
             }
             if constexpr (kPhiReg) phi_r[ti][tj] = v;
-            comp[ti][tj] = cv;
+            if constexpr (kComp) comp[ti][tj] = cv;
         }
     for (int e = tid; e < 3 * KP; e += kThreads) {
         const int v = e / KP, a = e % KP;
@@ -728,8 +731,13 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
+                    if constexpr (kComp) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
+                        for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) phi_r[ti][tj][r] = fmaf(-f3, oacc[ti][tj][r], phi_r[ti][tj][r]);
+                    }
                 }
             }
         }
@@ -985,17 +993,23 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     const int mt = wr + WR * ti;
                     if (mt >= NTK) continue;
                     const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
-                    f32x4 v = phi_get(ti, tj), cv = comp[ti][tj];
+                    f32x4 v = phi_get(ti, tj);
+                    if constexpr (kComp) {
+                        f32x4 cv = comp[ti][tj];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        // Kahan step; cmask = 0 turns it into the plain update
-                        const float y = fmaf(f1, dacc[ti][tj][r], fmaf(f2, ybc[r], -cv[r]));
-                        const float tt = v[r] + y;
-                        cv[r] = ((tt - v[r]) - y) * cmask;
-                        v[r] = tt;
+                        for (int r = 0; r < 4; ++r) {
+                            // Kahan step; cmask = 0 turns it into the plain update
+                            const float y = fmaf(f1, dacc[ti][tj][r], fmaf(f2, ybc[r], -cv[r]));
+                            const float tt = v[r] + y;
+                            cv[r] = ((tt - v[r]) - y) * cmask;
+                            v[r] = tt;
+                        }
+                        comp[ti][tj] = cv;
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v[r] += fmaf(f1, dacc[ti][tj][r], f2 * ybc[r]);
                     }
                     if constexpr (kPhiReg) phi_r[ti][tj] = v;
-                    comp[ti][tj] = cv;
                     M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
                 }
             }
@@ -1081,7 +1095,11 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                 const int a = mt * 16 + 4 * q + r;
                 if (a < k && i < k) {
                     Phi[(size_t)i * k + a] = phi_get(ti, tj)[r];
-                    if (Comp) Comp[(size_t)i * k + a] = g.compensated ? comp[ti][tj][r] : 0.0f;
+                    if constexpr (kComp) {
+                        if (Comp) Comp[(size_t)i * k + a] = g.compensated ? comp[ti][tj][r] : 0.0f;
+                    } else {
+                        if (Comp) Comp[(size_t)i * k + a] = 0.0f;
+                    }
                 }
             }
         }

@@ -11,7 +11,8 @@ one or on properties that hold at any size.
   step on the same BF16 rows (the BF16 step bar 3e-2); the full 50-pass BF16
   run (25,000 steps) against the FP64 oracle run from the same initial
   factors and permutations: relative factor error at most 1e-2 (the BF16 run
-  bar), and its residual within 2e-3 of the oracle run's.
+  bar), and its residual within 2e-3 of the oracle run's, with the
+  compensated and with the plain FP32 master update.
 * Documents, d = 10000, k = 50, 100000 documents, FP32: sketch and whitener
   (1e-8), three-view whitening on sampled rows (1e-6), the full 50-pass FP32
   STGD run (50,000 steps) against the oracle run (factor error 1e-4, the FP32
@@ -102,6 +103,18 @@ def test_graph_stgd_step_and_run_fullsize(graph):
     print(f"graph BF16 50-pass run: factor error {err:.3e}, R gpu {R_gpu:.5f} oracle {R_or:.5f}", flush=True)
     assert err <= 1e-2, err
     assert abs(R_gpu - R_or) < 2e-3, (R_gpu, R_or)
+    # the same run with the plain FP32 master update (the kernel variant that
+    # keeps no compensation terms): the same bars
+    pp = otm.SgdParams(k=k, batch=100, passes=50, y_dtype=otm.BF16, alpha0=0.5, beta0=1e-3, beta_tau=2500.0,
+                       ldy=Y.shape[1], compensated=False)
+    Phi = to_dev(Phi0.T.copy(), torch.float32)[None].contiguous()
+    otm.sgd_run(pp, n, Y, Y, Y, yb3, permd, Phi, nonfinite=flag)
+    R_plain = float(otm.residual(T, Phi).item())
+    err_plain = rel(host(Phi[0]).T, Ro)
+    print(f"graph BF16 50-pass run, plain update: factor error {err_plain:.3e}, R gpu {R_plain:.5f}", flush=True)
+    assert int(flag.item()) == 0
+    assert err_plain <= 1e-2, err_plain
+    assert abs(R_plain - R_or) < 2e-3, (R_plain, R_or)
 
 
 def test_documents_fullsize():

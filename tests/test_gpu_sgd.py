@@ -5,7 +5,9 @@ Bars (stated per precision):
 * FP32 step: the GPU update Phi1 - Phi0 matches the oracle's within 1e-5
   relative (Frobenius), i.e. the step is right to FP32 accumulation error;
 * BF16 step (Y stored in BF16, Phi and the exchanged G*G / Q rounded to BF16 as
-  matrix-core operands, FP32 accumulation): update within 3e-2 relative;
+  matrix-core operands, FP32 accumulation): update within 3e-2 relative, with
+  the compensated update and with the variant that keeps no compensation
+  terms;
 * FP32 run: factor error ||Phi_gpu - Phi_ref||_F / ||Phi_ref||_F <= 1e-4;
 * runs split at any step, restarts in one launch and per-pass snapshots are
   bit-identical to the corresponding single runs on the GPU.
@@ -61,7 +63,8 @@ def test_step_fp32(k, rows, alpha0):
 
 @pytest.mark.parametrize("k", [10, 64, 100, 128])
 @pytest.mark.parametrize("alpha0", [0.0, 1.0])
-def test_step_bf16(k, alpha0):
+@pytest.mark.parametrize("compensated", [True, False])
+def test_step_bf16(k, alpha0, compensated):
     rows = 100
     YA, YB, YC, ybar, Phi0 = _inputs(rows, k, seed=k + 7)
     YA, YB, YC = (bf16_round(x) for x in (YA, YB, YC))
@@ -70,7 +73,7 @@ def test_step_bf16(k, alpha0):
     ref = oracle.sgd_step(YA, YB, YC, ybar, Phi0, beta, alpha0)
     A, B, C = _dev_views(YA, YB, YC, k, otm.BF16)
     P = phi_rows(Phi0)
-    p = otm.SgdParams(k=k, batch=100, alpha0=alpha0, y_dtype=otm.BF16)
+    p = otm.SgdParams(k=k, batch=100, alpha0=alpha0, y_dtype=otm.BF16, compensated=compensated)
     otm.sgd_step(p, rows, A, B, C, to_dev(ybar), beta, P)
     torch.cuda.synchronize()
     assert rel(phi_cols(P) - Phi0, ref - Phi0) < 3e-2
