@@ -47,7 +47,9 @@ def correlation(Pi_hat: np.ndarray, Pi: np.ndarray) -> np.ndarray:
 def t_statistic(rho: np.ndarray, n: int) -> np.ndarray:
     """T = rho sqrt(n - 2) / sqrt(1 - rho^2) (Section 5.1); +-inf at |rho| = 1."""
     rho = np.asarray(rho, dtype=np.float64)
-    with np.errstate(divide="ignore"):
+    # both branches are evaluated: |rho| >= 1 (rounding can give 1 + ulp)
+    # divides by zero or takes the root of a negative there, and is discarded
+    with np.errstate(divide="ignore", invalid="ignore"):
         return np.where(np.abs(rho) >= 1.0, np.sign(rho) * np.inf, rho * np.sqrt(n - 2.0) / np.sqrt(1.0 - rho * rho))
 
 
