@@ -276,98 +276,247 @@ __global__ void orth_scale_kernel(const double* __restrict__ V, const double* __
 // Y Rinv has orthonormal columns.  info = 1 (pass 0) or |= 1 (pass 1) when a
 // pivot is not above 1e-14 of the largest diagonal entry; that pivot is then
 // replaced by the largest diagonal entry so the results stay finite.
+//
+// Blocked by panels of kCholNB columns, three barriers per panel in each
+// half instead of two per column:
+//  * factorization, per panel J = [j0, j1): wave 0 factors the diagonal block
+//    in registers (one lane per packed entry, columns exchanged by
+//    shuffles); every row below solves its kCholNB entries against it; the
+//    trailing rows take the rank-kCholNB update.  The updates of an entry
+//    are applied column by column in the same order as the unblocked
+//    right-looking algorithm.
+//  * inverse X = L^-1 in place, panels from the last: X[i][c] for the rows
+//    below the panel from X (X L)[i][c] = 0, i.e.
+//    X[i][c] = -(1/L_cc) sum_{c < l <= i} X[i][l] L[l][c], whose terms with
+//    l past the panel are split over S lanes of a wave; then one thread per
+//    column inverts the diagonal block from (L X)[r][c] = 0.  The new entries
+//    are held in registers (or a small LDS block) until every read of the
+//    panel's L entries is done.  The reciprocals 1/L_jj are kept from the
+//    factorization, so the inverse divides nowhere.
 constexpr int kCholN = 200;
 constexpr int kCholThreads = 1024;
+constexpr int kCholNB = 8;
+constexpr int kCholLoads = 8;      // global loads in flight per thread while filling LDS
 
 __device__ __forceinline__ int low_idx(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// lane p of the packed nb x nb block: (r, c) with p = r (r + 1) / 2 + c, c <= r
+__device__ __forceinline__ bool block_entry(int p, int nb, int& r, int& c) {
+    r = 0;
+    c = 0;
+    if (p >= nb * (nb + 1) / 2) return false;
+    while ((r + 1) * (r + 2) / 2 <= p) ++r;
+    c = p - r * (r + 1) / 2;
+    return true;
+}
 
 __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* __restrict__ G, int m,
                                                                  double* __restrict__ Rinv, int32_t* info, int pass) {
     __shared__ double sL[kCholN * (kCholN + 1) / 2];
-    __shared__ double colj[kCholN];   // copy of the current column: reads never alias the writes
+    __shared__ double s_rdiag[kCholN];                 // 1 / L_jj
+    __shared__ double s_xblk[kCholNB * kCholNB];       // inverse of a diagonal block, column-major
     __shared__ double s_dmax;
     __shared__ int s_bad;
     const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += kCholThreads) {
-        const int i = e / m, j = e % m;
-        if (j <= i) sL[low_idx(i, j)] = 0.5 * (G[e] + G[(size_t)j * m + i]);
+    const int lane = tid & 63;
+    // symmetrized lower triangle 0.5 (G[i][j] + G[j][i]) from coalesced reads
+    // of G in two passes (the lower entries, then the upper ones added); a
+    // thread's loads of a pass are issued together
+    for (int half = 0; half < 2; ++half) {
+        for (int base = 0; base < m * m; base += kCholThreads * kCholLoads) {
+            double g[kCholLoads];
+#pragma unroll
+            for (int u = 0; u < kCholLoads; ++u) {
+                const int e = base + u * kCholThreads + tid;
+                g[u] = (e < m * m) ? G[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kCholLoads; ++u) {
+                const int e = base + u * kCholThreads + tid;
+                if (e < m * m) {
+                    const int i = e / m, j = e % m;
+                    if (half == 0 && j <= i) sL[low_idx(i, j)] = (j == i) ? g[u] : 0.5 * g[u];
+                    if (half == 1 && j > i) sL[low_idx(j, i)] += 0.5 * g[u];
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) {
+    if (tid < 64) {
         double dm = 0.0;
-        for (int i = 0; i < m; ++i) dm = fmax(dm, sL[low_idx(i, i)]);
-        s_dmax = dm;
-        s_bad = 0;
+        for (int i = lane; i < m; i += 64) dm = fmax(dm, sL[low_idx(i, i)]);
+        for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+        if (lane == 0) {
+            s_dmax = dm;
+            s_bad = 0;
+        }
     }
     __syncthreads();
     const double dmax = s_dmax;
-    // right-looking Cholesky, one column per step.  The diagonal entry keeps
-    // the pivot (every thread takes its square root itself, so no step waits
-    // for one thread) until the loop ends.
-    for (int j = 0; j < m; ++j) {
-        double* cj = colj;
-        double dj = sL[low_idx(j, j)];
-        if (!(dj > 1e-14 * dmax)) {   // not positive definite to working precision: reported, pivot replaced
-            if (tid == 0) s_bad = 1;
-            dj = dmax > 0.0 ? dmax : 1.0;
-        }
-        const double inv = 1.0 / sqrt(dj);
-        for (int i = j + 1 + tid; i < m; i += kCholThreads) {
-            const double v = sL[low_idx(i, j)] * inv;
-            sL[low_idx(i, j)] = v;
-            cj[i] = v;
+    const double dfix = dmax > 0.0 ? dmax : 1.0;
+
+    for (int j0 = 0; j0 < m; j0 += kCholNB) {
+        const int nb = min(kCholNB, m - j0), j1 = j0 + nb;
+        // diagonal block, wave 0
+        if (tid < 64) {
+            int r, c;
+            const bool live = block_entry(lane, nb, r, c);
+            double v = live ? sL[low_idx(j0 + r, j0 + c)] : 0.0;
+            bool bad = false;
+            for (int cc = 0; cc < nb; ++cc) {
+                double d = __shfl(v, cc * (cc + 1) / 2 + cc);
+                if (!(d > 1e-14 * dmax)) {   // not positive definite to working precision: reported, pivot replaced
+                    bad = true;
+                    d = dfix;
+                }
+                const double sq = sqrt(d), inv = 1.0 / sq;
+                if (lane == 0) s_rdiag[j0 + cc] = inv;
+                if (live && c == cc) v = (r == cc) ? sq : v * inv;
+                const double lr = __shfl(v, r * (r + 1) / 2 + cc);   // L[r][cc]
+                const double lc = __shfl(v, c * (c + 1) / 2 + cc);   // L[c][cc]
+                if (live && c > cc) v -= lr * lc;
+            }
+            if (live) sL[low_idx(j0 + r, j0 + c)] = v;
+            if (bad && lane == 0) s_bad = 1;
         }
         __syncthreads();
-        // trailing update A[i][l] -= L[i][j] L[l][j], j < l <= i, S threads per row
-        const int w = m - j - 1;
+        // the panel's rows below the block.  Only the last panel can be
+        // narrower than kCholNB, and it has no rows below it, so this phase
+        // and the trailing update always work on full panels.
+        for (int i = j1 + tid; i < m; i += kCholThreads) {
+            double x[kCholNB];
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) x[c] = sL[low_idx(i, j0 + c)];
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) {
+                double sacc = x[c];
+#pragma unroll
+                for (int t = 0; t < c; ++t) sacc -= x[t] * sL[low_idx(j0 + c, j0 + t)];
+                x[c] = sacc * s_rdiag[j0 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) sL[low_idx(i, j0 + c)] = x[c];
+        }
+        __syncthreads();
+        // trailing update A[i][l] -= sum_c L[i][c] L[l][c], j1 <= l <= i.  Rows
+        // are taken in pairs (the r-th shortest with the r-th longest), S
+        // threads per pair, so every thread has about the same number of
+        // entries; two entries per iteration, loaded before either is stored.
+        const int w = m - j1;
         if (w > 0) {
-            const int S = max(1, kCholThreads / w);
-            const int row = tid / S, sub = tid % S;
-            if (row < w) {
-                const int i = j + 1 + row;
-                const double lij = cj[i];
-                double* Li = sL + low_idx(i, 0);
-                for (int l = j + 1 + sub; l <= i; l += S) Li[l] -= lij * cj[l];
+            const int pairs = (w + 1) / 2;
+            const int S = max(1, kCholThreads / pairs);
+            const int pr = tid / S, sub = tid % S;
+            if (pr < pairs) {
+                const int ia = j1 + pr, ib = m - 1 - pr;   // ia == ib: the middle row of an odd count
+                const int la = ia - j1 + 1, lb = (ib != ia) ? ib - j1 + 1 : 0;
+                double lia[kCholNB], lib[kCholNB];
+#pragma unroll
+                for (int c = 0; c < kCholNB; ++c) {
+                    lia[c] = sL[low_idx(ia, j0 + c)];
+                    lib[c] = sL[low_idx(ib, j0 + c)];
+                }
+                for (int t = sub; t < la + lb; t += 2 * S) {
+                    const int u = t + S;
+                    const bool two = u < la + lb;
+                    const bool fa = t < la, fb = u < la;
+                    const int l1 = j1 + (fa ? t : t - la), l2 = j1 + (fb ? u : u - la);
+                    double* p1 = sL + low_idx(fa ? ia : ib, l1);
+                    double* p2 = sL + low_idx(fb ? ia : ib, two ? l2 : l1);
+                    const double* L1 = sL + low_idx(l1, j0);
+                    const double* L2 = sL + low_idx(two ? l2 : l1, j0);
+                    double a1 = *p1, a2 = *p2;
+                    double x1[kCholNB], x2[kCholNB];
+#pragma unroll
+                    for (int c = 0; c < kCholNB; ++c) {
+                        x1[c] = L1[c];
+                        x2[c] = L2[c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < kCholNB; ++c) {
+                        a1 -= (fa ? lia[c] : lib[c]) * x1[c];
+                        a2 -= (fb ? lia[c] : lib[c]) * x2[c];
+                    }
+                    *p1 = a1;
+                    if (two) *p2 = a2;
+                }
             }
         }
         __syncthreads();
     }
-    for (int j = tid; j < m; j += kCholThreads) {   // pivots -> diagonal of L
-        const double dj = sL[low_idx(j, j)];
-        sL[low_idx(j, j)] = sqrt((dj > 1e-14 * dmax) ? dj : (dmax > 0.0 ? dmax : 1.0));
-    }
-    __syncthreads();
     if (tid == 0 && (pass == 0 || s_bad)) *info = s_bad;
-    // in-place inverse of L, last column first: with the trailing block already
-    // inverted, column j of L^-1 is -(1/L_jj) Linv[j+1:, j+1:] L[j+1:, j];
-    // each row's dot product is split over S lanes of one wave.  L_jj is read
-    // before the first barrier, so its inverse is written in the same phase
-    // as the column.
-    for (int j = m - 1; j >= 0; --j) {
-        double* cj = colj;
-        for (int i = j + 1 + tid; i < m; i += kCholThreads) cj[i] = sL[low_idx(i, j)];
-        const double djj = 1.0 / sL[low_idx(j, j)];
-        __syncthreads();
-        const int w = m - j - 1;
-        if (w > 0) {
-            int S = 64;
-            while (S > 1 && S * w > kCholThreads) S >>= 1;
-            const int row = tid / S, sub = tid % S;
-            double acc = 0.0;
-            const int i = j + 1 + row;
-            if (row < w) {
-                const double* Li = sL + low_idx(i, 0);
-                for (int l = j + 1 + sub; l <= i; l += S) acc += Li[l] * cj[l];
+
+    for (int jb = ((m - 1) / kCholNB) * kCholNB; jb >= 0; jb -= kCholNB) {
+        const int nb = min(kCholNB, m - jb), j1 = jb + nb;
+        const int w = m - j1;
+        // four lanes per row (at most 192 rows): measured faster than wider
+        // splits, whose shuffle reduction costs more than the shorter loop
+        int S = 4;
+        while (S > 1 && S * w > kCholThreads) S >>= 1;
+        const int row = tid / S, sub = tid % S;
+        const bool has_row = w > 0 && row < w;
+        const int i = j1 + row;
+        double xr[kCholNB];
+        if (w > 0) {   // a panel with rows below it is full (nb == kCholNB)
+            double z[kCholNB];
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) z[c] = 0.0;
+            if (has_row) {
+                const double* Xi = sL + low_idx(i, 0);
+                for (int l = j1 + sub; l <= i; l += S) {
+                    const double xil = Xi[l];
+                    const double* Ll = sL + low_idx(l, jb);
+#pragma unroll
+                    for (int c = 0; c < kCholNB; ++c) z[c] += xil * Ll[c];
+                }
             }
-            for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-            if (row < w && sub == 0) sL[low_idx(i, j)] = -djj * acc;
+            // every lane of a wave takes part (S lanes per row, S a power of two)
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c)
+                for (int o = S >> 1; o > 0; o >>= 1) z[c] += __shfl_xor(z[c], o);
+#pragma unroll
+            for (int c = kCholNB - 1; c >= 0; --c) {
+                double acc = z[c];
+#pragma unroll
+                for (int l = c + 1; l < kCholNB; ++l) acc += xr[l] * sL[low_idx(jb + l, jb + c)];
+                xr[c] = -acc * s_rdiag[jb + c];
+            }
         }
-        if (tid == 0) sL[low_idx(j, j)] = djj;
-        __syncthreads();   // colj is rewritten next
+        __syncthreads();   // every read of the panel's L entries is done
+        if (has_row && sub == 0) {
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) sL[low_idx(i, jb + c)] = xr[c];
+        }
+        // the diagonal block's inverse from L X = I: thread c of wave 0 takes
+        // column c, X[r][c] = -(1/L_rr) sum_{c <= l < r} L[r][l] X[l][c]; the
+        // block is overwritten once every column is done
+        if (tid < nb) {
+            const int c = tid;
+            double xc[kCholNB];
+#pragma unroll
+            for (int r = 0; r < kCholNB; ++r) {
+                xc[r] = 0.0;
+                if (r >= c && r < nb) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int l = 0; l < r; ++l)
+                        if (l >= c) acc += sL[low_idx(jb + r, jb + l)] * xc[l];
+                    xc[r] = (r == c) ? s_rdiag[jb + r] : -s_rdiag[jb + r] * acc;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kCholNB; ++r) s_xblk[c * kCholNB + r] = xc[r];
+        }
+        __syncthreads();
+        if (tid < nb * kCholNB) {
+            const int c = tid / kCholNB, r = tid % kCholNB;
+            if (r >= c && r < nb) sL[low_idx(jb + r, jb + c)] = s_xblk[c * kCholNB + r];
+        }
+        __syncthreads();
     }
     for (int e = tid; e < m * m; e += kCholThreads) {
-        const int c = e / m, i = e % m;
-        Rinv[e] = (i >= c) ? sL[low_idx(i, c)] : 0.0;
+        const int c = e / m, ii = e % m;
+        Rinv[e] = (ii >= c) ? sL[low_idx(ii, c)] : 0.0;
     }
 }
 

@@ -107,7 +107,8 @@ def test_power_sketch_chain(normalize):
     np.testing.assert_allclose(host(ev), evref, rtol=1e-9)
 
 
-@pytest.mark.parametrize("d,m", [(50, 1), (300, 7), (1000, 64), (5000, 200), (2000, 256)])
+@pytest.mark.parametrize("d,m", [(50, 1), (300, 7), (400, 13), (500, 37), (1000, 64), (3000, 100), (5000, 200),
+                                 (2000, 256)])
 def test_orthonormalize(d, m):
     """m <= 200: Cholesky QR gives the QR factor whose R has a positive
     diagonal, which is unique, so it must equal NumPy's QR after that sign fix.
