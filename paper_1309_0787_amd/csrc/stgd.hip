@@ -24,8 +24,10 @@ int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
 template <class M, int KP>
 int dispatch_staging(const SgdArgs& a, int restarts, bool aliased, hipStream_t st) {
     constexpr int s1 = staging_for<M, KP>(true), s3 = staging_for<M, KP>(false);
-    if (M::EPL != 1 && !a.compensated)
-        return aliased ? launch_sgd<M, KP, s1, false>(a, restarts, st) : launch_sgd<M, KP, s3, false>(a, restarts, st);
+    if constexpr (M::EPL != 1) {
+        if (!a.compensated)
+            return aliased ? launch_sgd<M, KP, s1, false>(a, restarts, st) : launch_sgd<M, KP, s3, false>(a, restarts, st);
+    }
     return aliased ? launch_sgd<M, KP, s1, true>(a, restarts, st) : launch_sgd<M, KP, s3, true>(a, restarts, st);
 }
 
