@@ -528,7 +528,10 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         const float beta = g.beta0 / (1.0f + static_cast<float>(t) * g.inv_tau);
 
         // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
-        commit(nb);
+        // (the plain BF16 variant writes the batch rows after the G product,
+        // whose LDS reads then do not queue behind them: 2% off the step; the
+        // others, with fuller registers, spill that way and write them first)
+        if constexpr (kComp) commit(nb);
         if constexpr (NSTAGE == 0) {
             if (tid < nb) {
                 int32_t r = nperm ? nrow : row0 + tid;
@@ -623,6 +626,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                             acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
             }
             }
+            if constexpr (!kComp) commit(nb);
             if (SCORE && t == g.end_step) {   // first scoring step: sum of G^3 over live entries
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
