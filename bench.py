@@ -351,7 +351,7 @@ WARM = dict(instances=50000, exact_share=0.8, sampled_n=2000, epochs=6, batch=25
 
 def train_warm_start(inst, pool_res, w) -> tuple:
     """The learned warm start trained on instances from the three workloads'
-    generators (cfg 5): 80% exact-moment instances of block models drawn by
+    generators: 80% exact-moment instances of block models drawn by
     the small graph, document and large graph generators (k = 10, 50, 100),
     20% sampled instances: seeded subsets of 2000 whitened rows of the
     benchmark graph with its planted directions as targets."""
