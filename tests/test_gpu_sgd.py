@@ -10,7 +10,8 @@ Bars (stated per precision):
   terms;
 * FP32 run: factor error ||Phi_gpu - Phi_ref||_F / ||Phi_ref||_F <= 1e-4;
 * runs split at any step, restarts in one launch and per-pass snapshots are
-  bit-identical to the corresponding single runs on the GPU.
+  bit-identical to the corresponding single runs on the GPU (FP32, and BF16
+  at k = 100 with and without compensation).
 """
 import numpy as np
 import pytest
@@ -184,6 +185,37 @@ def test_run_split_restarts_snapshots_bit_identical():
         otm.sgd_run(p, n, A, B, C, yb, pd[r], P2, end_step=spp)
         torch.cuda.synchronize()
         assert torch.equal(P2, snaps[r, 0])
+
+
+@pytest.mark.parametrize("compensated", [False, True])
+def test_run_bf16_split_restarts_bit_identical(compensated):
+    """BF16 rows, one shared view, k = 100 (the benchmark's kernel shape):
+    restarts in one launch equal separate runs split in two, with the
+    compensation carried over when it is on (the plain update keeps no state
+    besides Phi)."""
+    n, k, passes = 700, 100, 2
+    YA, _, _, ybar, _ = _inputs(n, k, seed=17, three=False)
+    YA, ybar = bf16_round(YA), f32_round(ybar)
+    A, _, _ = _dev_views(YA, YA, YA, k, otm.BF16)
+    yb = to_dev(ybar)
+    R = 2
+    perms = np.stack([synth.permutations(n, passes, seed=40 + r) for r in range(R)])
+    pd = to_dev(perms, torch.int32)
+    Phi0 = np.stack([f32_round(synth.initial_factors(k, seed=19, restart=r)).T for r in range(R)])
+    p = otm.SgdParams(k=k, batch=100, passes=passes, y_dtype=otm.BF16, alpha0=0.5, beta0=0.01, beta_tau=100.0,
+                      compensated=compensated)
+    spp = (n + 99) // 100
+    P_all = to_dev(Phi0)
+    otm.sgd_run(p, n, A, A, A, yb, pd, P_all, restarts=R, perm_stride=passes * n)
+    for r in range(R):
+        P1 = to_dev(Phi0[r])
+        comp = torch.zeros((k, k), dtype=torch.float32, device=dev())
+        cut = spp + 3
+        otm.sgd_run(p, n, A, A, A, yb, pd[r], P1, start_step=0, end_step=cut, Phi_comp=comp)
+        otm.sgd_run(p, n, A, A, A, yb, pd[r], P1, start_step=cut, end_step=-1, Phi_comp=comp)
+        torch.cuda.synchronize()
+        assert torch.equal(P1, P_all[r])
+        assert torch.isfinite(P1).all()
 
 
 def test_run_nonfinite_flag_and_bad_arguments():
