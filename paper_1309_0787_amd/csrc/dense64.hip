@@ -286,7 +286,7 @@ __global__ void orth_scale_kernel(const double* __restrict__ V, const double* __
 //    are applied column by column in the same order as the unblocked
 //    right-looking algorithm.
 //  * inverse X = L^-1 in place, panels from the last: X[i][c] for the rows
-//    below the panel from X (X L)[i][c] = 0, i.e.
+//    below the panel from (X L)[i][c] = 0, i.e.
 //    X[i][c] = -(1/L_cc) sum_{c < l <= i} X[i][l] L[l][c], whose terms with
 //    l past the panel are split over S lanes of a wave; then one thread per
 //    column inverts the diagonal block from (L X)[r][c] = 0.  The new entries
