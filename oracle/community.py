@@ -16,7 +16,7 @@ Eq. 2moment_graph:
 Nothing n x n is formed: the pseudo-inverse stays in factored low-rank form
 (Section 4.1) and every product is applied to a thin matrix.
 
-READINGS (listed with the others in the design notes):
+READINGS:
 * Pairs carries the factor 1/n_X of the moments; Z_B and Z_C do not depend on
   it.
 * The randomized pseudo-inverse (Section 4.2, algorithm "Randomized

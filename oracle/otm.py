@@ -5,7 +5,7 @@ and the benchmark's CPU-baseline leg may use it.
 
 Section references are to Huang, Niranjan, Hakeem, Anandkumar, "Online Tensor
 Methods for Learning Latent Variable Models".  Readings taken where the paper
-is silent or inconsistent are marked READING and listed in the design notes.
+is silent or inconsistent are marked READING where they are applied.
 """
 from __future__ import annotations
 
