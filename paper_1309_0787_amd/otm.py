@@ -204,6 +204,61 @@ def _ptr_rows(t) -> tuple[int, int]:
     return t.data_ptr(), t.stride(0)
 
 
+def _need(t, name: str, dtype, shape=None, min_rows: int | None = None):
+    """Refuses a tensor of another element type or shape than the entry point
+    reads: the C ABI takes bare pointers, so a mismatch would make a kernel
+    read or write outside the buffer.  shape entries of None match anything;
+    min_rows (instead of shape[0]) accepts longer buffers."""
+    if t is None:
+        raise OtmError(-1, f"{name} must not be None")
+    if t.dtype != dtype:
+        raise OtmError(-3, f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None:
+        bad = t.dim() != len(shape) or any(s is not None and int(a) != int(s) for a, s in zip(t.shape, shape))
+        if bad:
+            want = tuple("*" if s is None else int(s) for s in shape)
+            raise OtmError(-2, f"{name} must have shape {want}, got {tuple(t.shape)}")
+    if min_rows is not None and (t.dim() < 1 or t.shape[0] < min_rows):
+        raise OtmError(-2, f"{name} must have at least {min_rows} rows, got {tuple(t.shape)}")
+
+
+def _need_numel(t, name: str, dtype, numel: int):
+    if t is None:
+        raise OtmError(-1, f"{name} must not be None")
+    if t.dtype != dtype:
+        raise OtmError(-3, f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise OtmError(-2, f"{name} must hold {numel} values, got {t.numel()}")
+
+
+def _need_w(W, C):
+    if W.dtype not in (torch.float32, torch.bfloat16):
+        raise OtmError(-3, f"W must be FP32 or BF16, got {W.dtype}")
+    if W.dim() != 2 or W.shape[0] != C.n_cols:
+        raise OtmError(-2, f"W must have one row per column of C ({C.n_cols}), got {tuple(W.shape)}")
+
+
+def _beyond_capacity(p) -> bool:
+    """k or batch past what the kernels are compiled for: the library refuses
+    the call itself (OTM_ECAPACITY), before any buffer is read."""
+    return p.k > int(lib().otm_max_k()) or p.batch > int(lib().otm_max_batch())
+
+
+def _need_views(p, n: int, YA, YB, YC, ybar3):
+    """The three views of an STGD call: y_dtype, ldy columns, at least n rows;
+    ybar3 the 3 x k FP32 means."""
+    ldy = p.ldy if p.ldy else default_ldy(p.k)
+    dt = _TORCH_DTYPE[p.y_dtype]
+    for name, Y in (("YA", YA), ("YB", YB), ("YC", YC)):
+        _need(Y, name, dt, (None, ldy), min_rows=n)
+    _need_numel(ybar3, "ybar3", torch.float32, 3 * p.k)
+
+
+def _need_csr_pair(C, CT):
+    if CT.n_rows != C.n_cols or CT.n_cols != C.n_rows or CT.nnz != C.nnz:
+        raise OtmError(-2, "CT must be the transpose of C (n_cols x n_rows, same nnz)")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -285,6 +340,8 @@ def m2_apply(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float, S: tor
              info: torch.Tensor | None = None):
     """O = M2 S (FP64).  Raises OtmError if a document has fewer than 2 tokens
     (at once, or through check_info when the caller passes an info slot)."""
+    _need(S, "S", torch.float64, (C.n_cols, None))
+    _need_csr_pair(C, CT)
     d, kt = S.shape
     O = torch.empty((d, kt), dtype=torch.float64, device=S.device)
     info, deferred = _info_slot(info, S.device)
@@ -302,6 +359,7 @@ def m2_apply_select(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float,
     """O = M2 S for the column selection S[sel_rows[j], j] = sel_signs[j] (FP64)."""
     if sel_rows.dtype != torch.int32 or sel_signs.dtype != torch.float64 or sel_rows.numel() != sel_signs.numel():
         raise OtmError(-3, "sel_rows must be int32 and sel_signs FP64 of the same length")
+    _need_csr_pair(C, CT)
     kt = sel_rows.numel()
     d = C.n_cols
     O = torch.empty((d, kt), dtype=torch.float64, device=sel_rows.device)
@@ -316,6 +374,8 @@ def m2_apply_select(C: DeviceCSR, CT: DeviceCSR, normalize: bool, alpha0: float,
 
 
 def selection_dense(sel_rows: torch.Tensor, sel_signs: torch.Tensor, d: int, stream=None) -> torch.Tensor:
+    if sel_rows.dtype != torch.int32 or sel_signs.dtype != torch.float64 or sel_rows.numel() != sel_signs.numel():
+        raise OtmError(-3, "sel_rows must be int32 and sel_signs FP64 of the same length")
     kt = sel_rows.numel()
     S = torch.empty((d, kt), dtype=torch.float64, device=sel_rows.device)
     _check(lib().otm_selection_dense(_ptr(sel_rows), _ptr(sel_signs), d, kt, _ptr(S), _stream(stream)))
@@ -333,6 +393,8 @@ def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = 
     """(W FP64 d x k, evals FP64 k, W_lo in w_lo_dtype or None).  W_lo is the
     d x k view of a d x ldw_lo buffer (default: k rounded up to 16 bytes) whose
     padding columns hold 0.  Raises OtmNotPSD."""
+    _need(O, "O", torch.float64, (None, None))
+    _need(S, "S", torch.float64, tuple(O.shape))
     d, kt = O.shape
     W = torch.empty((d, k), dtype=torch.float64, device=O.device)
     ev = torch.empty(k, dtype=torch.float64, device=O.device)
@@ -352,6 +414,7 @@ def whitener(O: torch.Tensor, S: torch.Tensor, k: int, w_lo_dtype: int | None = 
 
 def orthonormalize(Y: torch.Tensor, stream=None, info: torch.Tensor | None = None) -> torch.Tensor:
     """Q = Y (Y^T Y)^(-1/2) (FP64)."""
+    _need(Y, "Y", torch.float64, (None, None))
     d, m = Y.shape
     Q = torch.empty_like(Y)
     info, deferred = _info_slot(info, Y.device)
@@ -413,6 +476,9 @@ class DevicePartition:
 
 def pairs_apply(G1T: DeviceCSR, G2: DeviceCSR, V: torch.Tensor, stream=None) -> torch.Tensor:
     """Pairs(Y1, Y2) V = (1/n_X) G[Y1, X] (G[X, Y2] V) (FP64)."""
+    _need(V, "V", torch.float64, (G2.n_cols, None))
+    if G1T.n_cols != G2.n_rows:
+        raise OtmError(-2, "G1T must have one column per sample row of G2")
     n2, m = V.shape
     out = torch.empty((G1T.n_rows, m), dtype=torch.float64, device=V.device)
     ws = _ws(lib().otm_pairs_apply_workspace(G2.n_rows, m), V.device)
@@ -435,7 +501,10 @@ class PinvFactors:
 def pinv_factors(J: torch.Tensor, K: torch.Tensor, S_left: torch.Tensor, k: int, stream=None,
                  info: torch.Tensor | None = None) -> PinvFactors:
     """Rank-k randomized pseudo-inverse of P from J = P S_right, K = P^T S_left."""
+    _need(J, "J", torch.float64, (None, None))
     n1, m = J.shape
+    _need(K, "K", torch.float64, (None, m))
+    _need(S_left, "S_left", torch.float64, (n1, m))
     n2 = K.shape[0]
     dev = J.device
     QJ = torch.empty((n1, k), dtype=torch.float64, device=dev)
@@ -454,6 +523,10 @@ def pinv_factors(J: torch.Tensor, K: torch.Tensor, S_left: torch.Tensor, k: int,
 def factored_apply(Q_in: torch.Tensor, core: torch.Tensor, trans: bool, Q_out: torch.Tensor, X: torch.Tensor,
                    stream=None) -> torch.Tensor:
     """Q_out M (Q_in^T X), M = core or core^T."""
+    _need(Q_in, "Q_in", torch.float64, (None, None))
+    _need(core, "core", torch.float64, (Q_in.shape[1], Q_in.shape[1]))
+    _need(Q_out, "Q_out", torch.float64, (None, Q_in.shape[1]))
+    _need(X, "X", torch.float64, (Q_in.shape[0], None))
     n_in, k = Q_in.shape
     n_out = Q_out.shape[0]
     m = X.shape[1]
@@ -466,6 +539,7 @@ def factored_apply(Q_in: torch.Tensor, core: torch.Tensor, trans: bool, Q_out: t
 
 def transition_t_apply(G: DevicePartition, F: PinvFactors, view: int, V: torch.Tensor, stream=None) -> torch.Tensor:
     """view 1: Z_B^T V (n_B x m); view 2: Z_C^T V (n_C x m)."""
+    _need(V, "V", torch.float64, (G.XA.n_cols, None))
     m = V.shape[1]
     rows = G.XB.n_cols if view == 1 else G.XC.n_cols
     out = torch.empty((rows, m), dtype=torch.float64, device=V.device)
@@ -478,6 +552,7 @@ def transition_t_apply(G: DevicePartition, F: PinvFactors, view: int, V: torch.T
 
 def m2_apply_four(G: DevicePartition, F: PinvFactors, alpha0: float, S: torch.Tensor, stream=None) -> torch.Tensor:
     """O = M2 S for the four-partition second moment (FP64)."""
+    _need(S, "S", torch.float64, (G.XA.n_cols, None))
     m = S.shape[1]
     O = torch.empty((G.XA.n_cols, m), dtype=torch.float64, device=S.device)
     gc = G.c()
@@ -503,6 +578,7 @@ def power_sketch_four(G: DevicePartition, F: PinvFactors, alpha0: float, S: torc
 def cast_rows(X: torch.Tensor, dtype: int, ld: int | None = None, stream=None) -> torch.Tensor:
     """FP64 rows to an F32/BF16 copy with row stride ld (default: 16-byte rows);
     returns the rows x cols view of the padded buffer."""
+    _need(X, "X", torch.float64, (None, None))
     rows, cols = X.shape
     ld = default_ldw(cols, dtype) if ld is None else int(ld)
     out = torch.empty((rows, ld), dtype=_TORCH_DTYPE[dtype], device=X.device)
@@ -519,6 +595,7 @@ def whiten(C: DeviceCSR, normalize: bool, W: torch.Tensor, y_dtype: int = F32, l
            want_ybar: bool = True, out: torch.Tensor | None = None, stream=None):
     """Y (n x ldy, y_dtype) and ybar (k FP32, or None).  W (d x k) may be a
     column slice of a row-padded buffer; its row stride is passed as ldw."""
+    _need_w(W, C)
     d, k = W.shape
     w_ptr, ldw = _ptr_rows(W)
     if out is not None:   # the row stride is the output's own
@@ -541,6 +618,7 @@ def whiten_noalloc(C: DeviceCSR, normalize: bool, W: torch.Tensor, Y: torch.Tens
                    y_dtype: int = F32, stream=None):
     """otm_whiten_noalloc into caller-given Y (n x ldy) and ybar (k FP32 or
     None): no workspace, nothing allocated by the library or here."""
+    _need_w(W, C)
     d, k = W.shape
     w_ptr, ldw = _ptr_rows(W)
     if Y.dim() != 2 or Y.shape[0] != C.n_rows or Y.dtype != _TORCH_DTYPE[y_dtype]:
@@ -574,6 +652,11 @@ class SgdParams:
 def sgd_step(p: SgdParams, rows: int, YA, YB, YC, ybar3: torch.Tensor, beta: float, Phi: torch.Tensor,
              Phi_comp: torch.Tensor | None = None, stream=None):
     """One STGD step on the first `rows` rows; Phi (k x k FP32, row i = phi_i) updated in place."""
+    if not _beyond_capacity(p):
+        _need_views(p, rows, YA, YB, YC, ybar3)
+        _need_numel(Phi, "Phi", torch.float32, p.k * p.k)
+        if Phi_comp is not None:
+            _need_numel(Phi_comp, "Phi_comp", torch.float32, p.k * p.k)
     cp = p.c()
     _check(lib().otm_sgd_step(ctypes.byref(cp), rows, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), float(beta),
                               _ptr(Phi), _ptr(Phi_comp), _stream(stream)))
@@ -605,6 +688,17 @@ def sgd_run(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, perms: torch.
     """Runs STGD steps [start_step, end_step) for `restarts` independent runs
     (Phi: restarts x k x k FP32, updated in place)."""
     check_perms(perms, n, p.passes, restarts, perm_stride)
+    if not _beyond_capacity(p):
+        _need_views(p, n, YA, YB, YC, ybar3)
+        kk = p.k * p.k
+        _need_numel(Phi, "Phi", torch.float32, restarts * kk)
+        if Phi_comp is not None:
+            _need_numel(Phi_comp, "Phi_comp", torch.float32, restarts * kk)
+        if snapshots is not None and (snapshots.dtype != torch.float32
+                                      or snapshots.numel() < restarts * p.passes * kk):
+            raise OtmError(-2, "snapshots must be FP32 with restarts x passes x k x k values")
+        if nonfinite is not None and (nonfinite.dtype != torch.int32 or nonfinite.numel() < 1):
+            raise OtmError(-3, "nonfinite must be an int32 tensor")
     cp = p.c()
     _check(lib().otm_sgd_run(ctypes.byref(cp), n, _ptr(YA), _ptr(YB), _ptr(YC), _ptr(ybar3), _ptr(perms),
                              perm_stride, restarts, start_step, end_step, _ptr(Phi), _ptr(Phi_comp),
@@ -616,6 +710,9 @@ def sgd_score(p: SgdParams, n: int, YA, YB, YC, ybar3: torch.Tensor, Phi: torch.
               stream=None) -> torch.Tensor:
     """score_r = sum_ij (phi_i^T phi_j)^3 - 2 sum_i T(phi_i, phi_i, phi_i) for each of
     the `restarts` factor matrices in Phi (restarts x k x k FP32); FP64 result."""
+    if not _beyond_capacity(p):
+        _need_views(p, n, YA, YB, YC, ybar3)
+        _need_numel(Phi, "Phi", torch.float32, restarts * p.k * p.k)
     score = torch.empty(restarts, dtype=torch.float64, device=Phi.device)
     ws = _ws(lib().otm_sgd_score_workspace(restarts), Phi.device)
     cp = p.c()
@@ -721,7 +818,9 @@ def sgd_autotune(ks, batch: int, cache_path: str, stream=None):
 # ------------------------------------------------------------------ a6
 def unwhiten_topics(W: torch.Tensor, Phi: torch.Tensor, theta: float = 1.0, stream=None,
                     info: torch.Tensor | None = None):
+    _need(W, "W", torch.float64, (None, None))
     d, k = W.shape
+    _need_numel(Phi, "Phi", torch.float32, k * k)
     mu = torch.empty((d, k), dtype=torch.float64, device=W.device)
     ah = torch.empty(k, dtype=torch.float64, device=W.device)
     lam = torch.empty(k, dtype=torch.float64, device=W.device)
@@ -735,6 +834,9 @@ def unwhiten_topics(W: torch.Tensor, Phi: torch.Tensor, theta: float = 1.0, stre
 
 
 def recover_pi(Y: torch.Tensor, k: int, Phi: torch.Tensor, theta: float = 1.0, tau: float = 0.0, stream=None):
+    if Y.dtype not in (torch.float32, torch.bfloat16) or Y.dim() != 2 or Y.shape[1] < k:
+        raise OtmError(-3, "Y must be n x ldy (ldy >= k) in FP32 or BF16")
+    _need_numel(Phi, "Phi", torch.float32, k * k)
     n, ldy = Y.shape
     Pi = torch.empty((k, n), dtype=torch.float32, device=Y.device)
     ws = _ws(lib().otm_recover_pi_workspace(k), Y.device)
@@ -775,6 +877,7 @@ def validate(Pi_hat: torch.Tensor, Pi: torch.Tensor, threshold: float = 0.01, st
 
 def bridgeness(Pi_hat: torch.Tensor, G: DeviceCSR | None = None, stream=None):
     """(b, b_degree or None) per node."""
+    _need(Pi_hat, "Pi_hat", torch.float32, (None, None))
     kh, n = Pi_hat.shape
     b = torch.empty(n, dtype=torch.float64, device=Pi_hat.device)
     bd = torch.empty(n, dtype=torch.float64, device=Pi_hat.device) if G is not None else None
@@ -797,6 +900,11 @@ def probe_mfma(dtype: int, iters: int, blocks: int, out: torch.Tensor, stream=No
 
 # ------------------------------------------------------------------ loss
 def tensor_form(YA, YB, YC, k: int, ybar3: torch.Tensor, alpha0: float, stream=None):
+    if YA.dtype not in (torch.float32, torch.bfloat16) or YA.dim() != 2 or YA.shape[1] < k:
+        raise OtmError(-3, "YA must be n x ldy (ldy >= k) in FP32 or BF16")
+    _need(YB, "YB", YA.dtype, tuple(YA.shape))
+    _need(YC, "YC", YA.dtype, tuple(YA.shape))
+    _need_numel(ybar3, "ybar3", torch.float32, 3 * k)
     n, ldy = YA.shape
     T = torch.empty((k, k, k), dtype=torch.float64, device=YA.device)
     _check(lib().otm_tensor_form(_ptr(YA), _ptr(YB), _ptr(YC), _DTYPE_CODE[YA.dtype], ldy, n, k, _ptr(ybar3),
@@ -806,6 +914,9 @@ def tensor_form(YA, YB, YC, k: int, ybar3: torch.Tensor, alpha0: float, stream=N
 
 def residual(T: torch.Tensor, Phis: torch.Tensor, stream=None):
     k = T.shape[0]
+    _need(T, "T", torch.float64, (k, k, k))
+    if Phis.dtype != torch.float32 or Phis.numel() % (k * k) != 0:
+        raise OtmError(-3, "Phis must be FP32 with a multiple of k x k values")
     Phis = Phis.reshape(-1, k, k)
     cnt = Phis.shape[0]
     R = torch.empty(cnt, dtype=torch.float64, device=T.device)
