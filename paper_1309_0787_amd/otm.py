@@ -936,6 +936,15 @@ def ws_dims() -> dict:
 def ws_sketch(YA, YB, YC, k: int, ybar3: torch.Tensor, alpha0: float, Theta: torch.Tensor, S: torch.Tensor | None = None,
               stream=None) -> torch.Tensor:
     """S_r = T(I, I, theta_r), r = 0..3 (4 x lds x lds FP32; lds = S.shape[-1])."""
+    if YA.dtype not in (torch.float32, torch.bfloat16) or YA.dim() != 2 or YA.shape[1] < k:
+        raise OtmError(-3, "YA must be n x ldy (ldy >= k) in FP32 or BF16")
+    _need(YB, "YB", YA.dtype, tuple(YA.shape))
+    _need(YC, "YC", YA.dtype, tuple(YA.shape))
+    _need_numel(ybar3, "ybar3", torch.float32, 3 * k)
+    _need_numel(Theta, "Theta", torch.float32, 4 * k)
+    if S is not None and (S.dtype != torch.float32 or S.dim() != 3 or S.shape[0] != 4 or S.shape[1] != S.shape[2]
+                          or S.shape[2] < k):
+        raise OtmError(-2, "S must be 4 x lds x lds FP32 with lds >= k")
     n, ldy = YA.shape
     if S is None:
         S = torch.zeros((4, k, k), dtype=torch.float32, device=YA.device)
@@ -950,6 +959,9 @@ def ws_frames(ks: torch.Tensor, S: torch.Tensor, Theta: torch.Tensor, stream=Non
     """Canonical frames and network inputs: returns (Q, sigma, X, info)."""
     d = ws_dims()
     cnt = ks.numel()
+    _need_numel(ks, "ks", torch.int32, cnt)
+    _need_numel(S, "S", torch.float32, cnt * 4 * d["P"] * d["P"])
+    _need_numel(Theta, "Theta", torch.float32, cnt * d["P"] * 4)
     dev = S.device
     Q = torch.empty((cnt, d["P"], d["P"]), dtype=torch.float32, device=dev)
     sig = torch.empty(cnt, dtype=torch.float32, device=dev)
@@ -963,14 +975,25 @@ def ws_frames(ks: torch.Tensor, S: torch.Tensor, Theta: torch.Tensor, stream=Non
 
 def ws_target(ks, Q, sigma, U, lam, stream=None) -> torch.Tensor:
     cnt = ks.numel()
-    P = Q.shape[-1]
+    P = ws_dims()["P"]
+    _need_numel(ks, "ks", torch.int32, cnt)
+    _need_numel(Q, "Q", torch.float32, cnt * P * P)
+    _need_numel(sigma, "sigma", torch.float32, cnt)
+    _need_numel(U, "U", torch.float32, cnt * P * P)
+    _need_numel(lam, "lam", torch.float32, cnt * P)
     tgt = torch.empty((cnt, P * P), dtype=torch.float32, device=Q.device)
     _check(lib().otm_ws_target(cnt, _ptr(ks), _ptr(Q), _ptr(sigma), _ptr(U), _ptr(lam), _ptr(tgt), _stream(stream)))
     return tgt
 
 
+def _need_mlp(d, params, X):
+    _need_numel(params, "params", torch.float32, d["n_params"])
+    _need(X, "X", torch.float32, (None, d["n_in"]))
+
+
 def mlp_forward(params, X, stream=None):
     d = ws_dims()
+    _need_mlp(d, params, X)
     B = X.shape[0]
     H = torch.empty((B, d["hidden"]), dtype=torch.float32, device=X.device)
     out = torch.empty((B, d["n_out"]), dtype=torch.float32, device=X.device)
@@ -980,7 +1003,13 @@ def mlp_forward(params, X, stream=None):
 
 
 def mlp_backward(params, X, H, dout, grads=None, stream=None):
+    d = ws_dims()
+    _need_mlp(d, params, X)
     B = X.shape[0]
+    _need(H, "H", torch.float32, (B, d["hidden"]))
+    _need(dout, "dout", torch.float32, (B, d["n_out"]))
+    if grads is not None:
+        _need_numel(grads, "grads", torch.float32, d["n_params"])
     if grads is None:
         grads = torch.empty_like(params)
     ws = _ws(lib().otm_mlp_workspace(B), X.device)
@@ -990,11 +1019,15 @@ def mlp_backward(params, X, H, dout, grads=None, stream=None):
 
 
 def mlp_adam(params, grads, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    npar = ws_dims()["n_params"]
+    for name, t_ in (("params", params), ("grads", grads), ("m", m), ("v", v)):
+        _need_numel(t_, name, torch.float32, npar)
     _check(lib().otm_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr), float(beta1),
                               float(beta2), float(eps), _stream(stream)))
 
 
 def mlp_to_bf16(params, stream=None) -> torch.Tensor:
+    _need_numel(params, "params", torch.float32, ws_dims()["n_params"])
     pb = torch.empty(params.numel(), dtype=torch.bfloat16, device=params.device)
     _check(lib().otm_mlp_to_bf16(_ptr(params), _ptr(pb), _stream(stream)))
     return pb
@@ -1002,6 +1035,8 @@ def mlp_to_bf16(params, stream=None) -> torch.Tensor:
 
 def mlp_forward_bf16(params_bf16, params, X, stream=None) -> torch.Tensor:
     d = ws_dims()
+    _need_mlp(d, params, X)
+    _need_numel(params_bf16, "params_bf16", torch.bfloat16, d["n_params"])
     B = X.shape[0]
     out = torch.empty((B, d["n_out"]), dtype=torch.float32, device=X.device)
     ws = _ws(lib().otm_mlp_bf16_workspace(B), X.device)
@@ -1012,6 +1047,10 @@ def mlp_forward_bf16(params_bf16, params, X, stream=None) -> torch.Tensor:
 
 def ws_mse(ks, live: int, out, target, stream=None):
     cnt = ks.numel()
+    n_out = ws_dims()["n_out"]
+    _need_numel(ks, "ks", torch.int32, cnt)
+    _need_numel(out, "out", torch.float32, cnt * n_out)
+    _need_numel(target, "target", torch.float32, cnt * n_out)
     loss = torch.empty(1, dtype=torch.float64, device=out.device)
     dout = torch.empty_like(out)
     ws = _ws(lib().otm_ws_mse_workspace(cnt), out.device)
@@ -1022,7 +1061,12 @@ def ws_mse(ks, live: int, out, target, stream=None):
 
 def ws_factors(ks, out, Q, sigma, stream=None) -> torch.Tensor:
     cnt = ks.numel()
-    P = Q.shape[-1]
+    d = ws_dims()
+    P = d["P"]
+    _need_numel(ks, "ks", torch.int32, cnt)
+    _need_numel(out, "out", torch.float32, cnt * d["n_out"])
+    _need_numel(Q, "Q", torch.float32, cnt * P * P)
+    _need_numel(sigma, "sigma", torch.float32, cnt)
     Phi = torch.zeros((cnt, P * P), dtype=torch.float32, device=out.device)
     _check(lib().otm_ws_factors(cnt, _ptr(ks), _ptr(out), _ptr(Q), _ptr(sigma), _ptr(Phi), _stream(stream)))
     return Phi

@@ -104,3 +104,22 @@ def test_stgd_views_factors_and_means_are_checked():
         with pytest.raises(otm.OtmError) as e:
             otm.sgd_run(p, n, a["YA"], a["YB"], a["YC"], a["ybar3"], None, a["Phi"])
         assert e.value.status == status, over
+
+
+def test_warm_start_buffers_are_checked():
+    d = otm.ws_dims()
+    params = torch.zeros(d["n_params"], dtype=torch.float32)
+    with pytest.raises(otm.OtmError) as e:
+        otm.mlp_forward(params, torch.zeros((2, d["n_in"] - 1), dtype=torch.float32))
+    assert e.value.status == -2
+    with pytest.raises(otm.OtmError) as e:
+        otm.mlp_forward(params[:-1], torch.zeros((2, d["n_in"]), dtype=torch.float32))
+    assert e.value.status == -2
+    with pytest.raises(otm.OtmError) as e:
+        otm.mlp_adam(params, params, params, params.double(), 1, 1e-3)
+    assert e.value.status == -3
+    ks = torch.tensor([4, 5], dtype=torch.int32)
+    with pytest.raises(otm.OtmError) as e:
+        otm.ws_frames(ks, torch.zeros((1, 4, d["P"], d["P"]), dtype=torch.float32),
+                      torch.zeros((2, d["P"], 4), dtype=torch.float32))
+    assert e.value.status == -2
