@@ -3,7 +3,7 @@
 //
 //   PA = YA Phi, PB = YB Phi                       (batch x k, matrix cores)
 //   mA = Phi^T ybarA, mB = Phi^T ybarB             (k, vector ALU)
-//   H  = PA * PB,  s = column sums of H            (wave shuffles)
+//   H  = PA * PB,  s = column sums of H            (cross-lane swaps)
 //   Q  = a H - b PA diag(mB) - b diag(mA) PB
 //   D  = YC^T Q / B + ybarC (c mA*mB - b s / B)^T  (matrix cores)
 //   G  = Phi^T Phi,  O = Phi (G * G)               (matrix cores)
@@ -18,9 +18,12 @@
 // part of the update enters the register master copy right after O is formed
 // (so O does not stay live), the direction part at the end of the step; the
 // LDS operand copies keep the old Phi for every product of the step.  LDS
-// holds operand copies of Phi (phi_i-major, plus an a-major copy for BF16
-// fragments), a buffer that carries G*G and then Q from the accumulator layout
-// to the operand layout, the mini-batch of whitened rows, and small vectors.
+// holds the operand copy of Phi (phi_i-major; BF16 products that need it the
+// other way round use transposing LDS reads), a buffer that carries G*G and
+// then Q from the accumulator layout to the operand layout, the mini-batch of
+// whitened rows, and small vectors.  In BF16 the rows of the Phi copy and of
+// the buffer are stored with a column permutation that keeps both the
+// fragment reads and the tile stores free of most bank conflicts.
 //
 // Batch staging (NSTAGE = 1 for one shared view, 3 for three views): the rows
 // of step t+1 are fetched into registers while step t computes (their indices
@@ -100,6 +103,8 @@ struct MmaF32 {
     }
     __device__ static void store4(Op* p, f32x4 v) { *reinterpret_cast<f32x4*>(p) = v; }
     __device__ static f32x4 load4(const Op* p) { return *reinterpret_cast<const f32x4*>(p); }
+    // column permutation of row r of the Phi copy and the exchange buffer (none in FP32)
+    __device__ static constexpr int sw(int) { return 0; }
 };
 
 struct MmaBF16 {
@@ -109,14 +114,24 @@ struct MmaBF16 {
     using Chunk = bf16x8;
     static constexpr int KI = 32;
     static constexpr int EPL = 8;
-    // LDS row padding: rows 288 bytes apart, 8 banks of shift per row (4 or
-    // 12 banks measured about 4% slower per step at k = 128)
+    // LDS row padding: rows 288 bytes apart.  Of the pitches 256 to 336
+    // bytes this is the only one at which a fragment read (lane l: row l % 16,
+    // 16-byte chunk l / 16) runs without bank conflicts on gfx950 (4 cycles
+    // per wave against 8 to 32); 272 and 304 were about 4% slower per step
     static constexpr int SPAD = 16;
     static constexpr int CH = 8;
     __device__ static f32x4 mma(Frag a, Frag b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
     __device__ static Frag lds(const Op* p) { return *reinterpret_cast<const bf16x8*>(p); }
+    // Column permutation of row r of the Phi copy and the exchange buffer: rows
+    // with bit 2 set swap their 16-byte chunks in pairs.  At the 288-byte
+    // pitch the 8-byte stores of a product's output tile (lane l: row l % 16,
+    // piece l / 16) hit each bank twice as often as they need to (16 cycles
+    // per wave); with the permutation they take 8 (a contiguous 8-byte store
+    // takes 6.6), while the fragment reads stay conflict-free (measured on
+    // gfx950; BF16 k = 100 step 5.02 -> 4.85 us).
+    __device__ static constexpr int sw(int r) { return ((r >> 2) & 1) << 3; }
     // Fragment of a matrix stored the other way round: lane l receives
     // X[8 (l/16) + e][l % 16], e < 8, where X[r][c] = x[r * stride + c] in
     // LDS.  Two transposing 8-byte reads (rows 0-3 and 4-7 of the lane's
@@ -131,6 +146,19 @@ struct MmaBF16 {
         const Op* p = x + (8 * (lane >> 4) + ((lane >> 2) & 3)) * stride + 4 * (lane & 3);
         const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p));
         const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * stride));
+        const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_bit_cast(Frag, v);
+    }
+    // lds_t on a permuted array (sw above), x at a row that is a multiple of 8
+    // and a column that is a multiple of 16: the first read's rows keep their
+    // order, the second read's rows (bit 2 set) have their chunks swapped
+    __device__ static Frag lds_t_sw(const Op* x, int stride, int lane) {
+        typedef short s16x4 __attribute__((ext_vector_type(4)));
+        typedef short s16x8 __attribute__((ext_vector_type(8)));
+        typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+        const Op* p = x + (8 * (lane >> 4) + ((lane >> 2) & 3)) * stride;
+        const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * (lane & 3)));
+        const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * stride + ((4 * (lane & 3)) ^ 8)));
         const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         return __builtin_bit_cast(Frag, v);
     }
@@ -255,6 +283,24 @@ constexpr int staging_for(bool aliased) {
     return smem_bytes<M, KP, 3, WR>() <= kLdsLimit ? 3 : 0;
 }
 
+// x + (x of lane l ^ 1, l ^ 16 or l ^ 32) in every lane l, without a round
+// trip through the LDS crossbar: a quad-permutation DPP move for l ^ 1, and
+// gfx950's row swap (16 lanes) and half swap (32 lanes) for the others.  Both
+// lanes of a pair get the same sum, since addition commutes, so the result
+// equals that of a shuffle-based butterfly bit for bit.
+__device__ __forceinline__ float add_xor1(float x) {
+    const int p = __builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false);   // [1, 0, 3, 2]
+    return x + __int_as_float(p);
+}
+__device__ __forceinline__ float add_xor16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float add_xor32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // One whole run of restart r_id of the problem in g, by the calling workgroup.
 template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true>
 __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
@@ -286,8 +332,26 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6) & (kWaves - 1);
     // the masks give the compiler the ranges of wr and wc, so tile guards that
     // always hold for this KP fold away
-    const int wr = (w / WC) & (WR - 1), wc = w & (WC - 1);
+    // Waves w and w + 4 run on the same SIMD (the CU deals a workgroup's waves
+    // out to its four SIMDs in turn).  When k is not a multiple of 64 the last
+    // tile row or column of the wave grid is short, so with WR >= 4 the two
+    // waves of a SIMD take the same wave row and both wave columns: the SIMDs
+    // then carry equal shares of the MFMA work (FP32 k = 100: 44.6 -> 42.2 us
+    // per step, results unchanged, as every tile keeps its summation order).
+    int wr, wc;
+    if constexpr (WR >= 4) {
+        wr = ((w & 3) + 4 * ((w >> 2) & (WR / 4 - 1))) & (WR - 1);
+        wc = ((w >> 2) / (WR / 4)) & (WC - 1);
+    } else {
+        wr = (w / WC) & (WR - 1);
+        wc = w & (WC - 1);
+    }
     const int l16 = lane & 15, q = lane >> 4;
+    // column permutation of every row 16 m + l16 of the Phi copy and the
+    // exchange buffer, folded into the lane's fragment column (cq) and output
+    // column (sq): k0 + cq and 16 mt + sq keep the tile offsets additive
+    const int swl = M::sw(l16);
+    const int cq = (q * M::EPL) ^ swl, sq = (4 * q) ^ swl;
 
     const int k = g.k;
     const int n = g.n, ldy = g.ldy, B = g.batch;
@@ -339,7 +403,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                         if (Comp && g.compensated) cv[r] = Comp[(size_t)i * k + a];
                     }
                 }
-                M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
+                M::store4(&sm.phi[i * SP + (mt * 16 + sq)], v);
             }
             if constexpr (kPhiReg) phi_r[ti][tj] = v;
             if constexpr (kComp) comp[ti][tj] = cv;
@@ -350,7 +414,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     }
     for (int e = tid; e < 2 * SP; e += kThreads) {
         const int v = e / SP, a = e % SP;
-        sm.yfold[e] = M::to_op((a < k) ? g.ybar[v * k + a] : 0.0f);
+        sm.yfold[v * SP + (a ^ M::sw(k + v))] = M::to_op((a < k) ? g.ybar[v * k + a] : 0.0f);
     }
     // rows of the second operand of Phi^T Phi: component i, or a mean at k, k+1
     const Op* grow[TC];
@@ -519,13 +583,16 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     __syncthreads();
 
     double score_g = 0.0, score_t = 0.0;   // scoring pass: sum G^3 and sum T(phi, phi, phi), per lane
+    // step size of the coming step; the next one is computed during the O
+    // product, whose matrix cores leave the vector ALU idle
+    float beta_t = g.beta0 / (1.0f + static_cast<float>(g.start_step) * g.inv_tau);
     for (int t = g.start_step; t < t_end; ++t) {
         const bool train = !SCORE || t < g.end_step;
         const int pass = train ? t / g.spp : 0;
         const int s = train ? t - pass * g.spp : t - g.end_step;
         const int row0 = s * B;
         const int nb = min(B, n - row0);
-        const float beta = g.beta0 / (1.0f + static_cast<float>(t) * g.inv_tau);
+        const float beta = beta_t;
 
         // ================= phase 1: batch rows, G = Phi^T Phi -> G*G (and mA, mB)
         // (the plain BF16 variant writes the batch rows after the G product,
@@ -548,17 +615,18 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             float acc = 0.f;
             if (i < KP) {
                 constexpr int half = KP >> 1;
-                const Op* prow = &sm.phi[i * SP + h * half];
+                const Op* prow = &sm.phi[i * SP];
+                const int psw = M::sw(i);
                 const float* yb = &sm.ybar[v * KP + h * half];
 #pragma unroll
                 for (int a = 0; a < half; a += 8) {
                     float x[8];
                     if constexpr (M::EPL == 8) {
-                        const bf16x8 pv = *reinterpret_cast<const bf16x8*>(prow + a);
+                        const bf16x8 pv = *reinterpret_cast<const bf16x8*>(prow + ((h * half + a) ^ psw));
 #pragma unroll
                         for (int e = 0; e < 8; ++e) x[e] = M::op_to_f(pv[e]);
                     } else {
-                        const f32x4 p0 = M::load4(prow + a), p1 = M::load4(prow + a + 4);
+                        const f32x4 p0 = M::load4(prow + h * half + a), p1 = M::load4(prow + h * half + a + 4);
 #pragma unroll
                         for (int e = 0; e < 4; ++e) { x[e] = p0[e]; x[e + 4] = p1[e]; }
                     }
@@ -568,7 +636,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                            x[4] * y1[0] + x[5] * y1[1] + x[6] * y1[2] + x[7] * y1[3];
                 }
             }
-            acc += __shfl_xor(acc, 1);
+            acc = add_xor1(acc);
             if (h == 0 && i < KP) sm.m[v * KP + i] = acc;
         }
         {
@@ -611,12 +679,12 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + WR * ti;
-                    fa[ti] = (mt < NTK) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + k0 + q * M::EPL]) : M::zero_frag();
+                    fa[ti] = (mt < NTK) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + (k0 + cq)]) : M::zero_frag();
                 }
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(grow[tj] + k0 + q * M::EPL) : M::zero_frag();
+                    fb[tj] = (nt < NTK) ? M::lds(grow[tj] + (k0 + cq)) : M::zero_frag();
                 }
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
@@ -653,7 +721,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     if (mt < NTK && nt < NTK) {
                         const int i = nt * 16 + l16;
                         const f32x4 gv = acc[ti][tj];
-                        M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], gv * gv);
+                        M::store4(&sm.buf[i * SB + (mt * 16 + sq)], gv * gv);
                         if (mfold && (i == k || i == k + 1))
                             *reinterpret_cast<f32x4*>(&sm.m[(i - k) * KP + mt * 16 + 4 * q]) = gv;
                     }
@@ -662,6 +730,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         __syncthreads();
 
         // ================= phase 2: O = Phi (G*G), applied to the master copy at once
+        beta_t = g.beta0 / (1.0f + static_cast<float>(t + 1) * g.inv_tau);   // the next step's
         f32x4 oacc[TRK][TC];
 #pragma unroll
         for (int ti = 0; ti < TRK; ++ti)
@@ -705,7 +774,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 if (mt < NTK) {
                     // Phi[a][i], a = 16 mt + lane % 16, i = k0 + EPL q + e, from the
                     // component-major copy
-                    fa[ti] = M::lds_t(&sm.phi[k0 * SP + mt * 16], SP, lane);
+                    fa[ti] = M::lds_t_sw(&sm.phi[k0 * SP + mt * 16], SP, lane);
                 } else {
                     fa[ti] = M::zero_frag();
                 }
@@ -713,7 +782,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + WC * tj;
-                fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
+                fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
             }
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti)
@@ -748,9 +817,14 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         __syncthreads();   // every read of G*G is done: the buffer takes Q next
 
         // rows of step t+1 start their trip from global memory now, then the
-        // row indices of step t+2
-        issue_data();
-        issue_index(t + 2);
+        // row indices of step t+2 (the plain BF16 one-view variant issues them
+        // after its batch product instead, so that product's operand reads
+        // are the first thing after the barrier: 1-2% off the step)
+        constexpr bool kLateIssue = M::EPL != 1 && NSTAGE == 1 && !kComp;
+        if constexpr (!kLateIssue) {
+            issue_data();
+            issue_index(t + 2);
+        }
         if constexpr (NSTAGE == 0) next_row(t + 1);
 
         // ================= phase 3: PA, PB one tile row at a time -> Q into the
@@ -786,7 +860,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        fphi[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL])
+                        fphi[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + (k0 + cq)])
                                               : M::zero_frag();
                     }
 #pragma unroll
@@ -798,6 +872,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                             if (wc + WC * tj < NTK) pt[ti][tj] = M::mma(fa, fphi[tj], pt[ti][tj]);
                     }
                 }
+                issue_data();
+                issue_index(t + 2);
 #pragma unroll
                 for (int ti = 0; ti < kTR; ++ti) {
                     const int mt = wr + WR * ti;
@@ -813,7 +889,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                             colsum[tj] = fmaf(xa, xa, colsum[tj]);
                             qv[r] = xa * fmaf(al[tj], xa, -(bmA[tj] + bmB[tj]));
                         }
-                        M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], qv);
+                        M::store4(&sm.buf[i * SB + (mt * 16 + sq)], qv);
                     }
                 }
             } else {
@@ -881,7 +957,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
                         if (nt < NTK) {
-                            const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + k0 + q * M::EPL]);
+                            const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + (k0 + cq)]);
                             pa[tj] = M::mma(fa, fphi, pa[tj]);
                             if constexpr (NSTAGE != 1) pb[tj] = M::mma(fbv, fphi, pb[tj]);
                         }
@@ -906,7 +982,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                             qv[r] = fmaf(xa, fmaf(al[tj], xb, -bmB[tj]), -bmA[tj] * xb);
                         }
                     }
-                    M::store4(&sm.buf[i * SB + mt * 16 + 4 * q], qv);
+                    M::store4(&sm.buf[i * SB + (mt * 16 + sq)], qv);
                 }
             }
             }
@@ -914,8 +990,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + WC * tj;
                 if (nt >= NTK) continue;
-                colsum[tj] += __shfl_xor(colsum[tj], 16);
-                colsum[tj] += __shfl_xor(colsum[tj], 32);
+                colsum[tj] = add_xor16(colsum[tj]);
+                colsum[tj] = add_xor32(colsum[tj]);
                 if (q == 0) sm.s[wr * KP + nt * 16 + l16] = colsum[tj];
             }
         }
@@ -1003,7 +1079,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + k0 + q * M::EPL]) : M::zero_frag();
+                    fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
                 }
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
@@ -1063,7 +1139,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                         for (int r = 0; r < 4; ++r) v[r] += fmaf(f1, dacc[ti][tj][r], f2 * ybc[r]);
                     }
                     if constexpr (kPhiReg) phi_r[ti][tj] = v;
-                    M::store4(&sm.phi[i * SP + mt * 16 + 4 * q], v);
+                    M::store4(&sm.phi[i * SP + (mt * 16 + sq)], v);
                 }
             }
             if (train && (s == g.spp - 1 || t + 1 == g.end_step)) {
