@@ -330,14 +330,14 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const int lane = tid & 63;
     // wave index in a scalar register: every tile guard below is a scalar branch
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6) & (kWaves - 1);
-    // the masks give the compiler the ranges of wr and wc, so tile guards that
-    // always hold for this KP fold away
     // Waves w and w + 4 run on the same SIMD (the CU deals a workgroup's waves
-    // out to its four SIMDs in turn).  When k is not a multiple of 64 the last
-    // tile row or column of the wave grid is short, so with WR >= 4 the two
-    // waves of a SIMD take the same wave row and both wave columns: the SIMDs
-    // then carry equal shares of the MFMA work (FP32 k = 100: 44.6 -> 42.2 us
-    // per step, results unchanged, as every tile keeps its summation order).
+    // out to its four SIMDs in turn).  With WR >= 4 the two waves of a SIMD
+    // take the same wave row and both wave columns, so when the tile count
+    // leaves the last wave row or column short (k = 100: 7 tiles) the four
+    // SIMDs still carry near-equal shares of the MFMA work (FP32 k = 100:
+    // 44.6 -> 42.2 us per step; every tile keeps its summation order, so the
+    // results are unchanged).  The masks give the compiler the ranges of wr
+    // and wc, so tile guards that always hold for this KP fold away.
     int wr, wc;
     if constexpr (WR >= 4) {
         wr = ((w & 3) + 4 * ((w >> 2) & (WR / 4 - 1))) & (WR - 1);
