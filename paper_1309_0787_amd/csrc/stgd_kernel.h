@@ -350,7 +350,11 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     // column permutation of every row 16 m + l16 of the Phi copy and the
     // exchange buffer, folded into the lane's fragment column (cq) and output
     // column (sq): k0 + cq and 16 mt + sq keep the tile offsets additive
-    const int swl = M::sw(l16);
+    // (not for three staged views at KP = 96, where the extra per-lane offsets
+    // cost spills: that step measured 5.6 us plain without it, 5.9 with it)
+    constexpr bool kPerm = M::EPL != 1 && !(NSTAGE == 3 && KP >= 96);
+    auto swz = [](int r) { return kPerm ? M::sw(r) : 0; };
+    const int swl = swz(l16);
     const int cq = (q * M::EPL) ^ swl, sq = (4 * q) ^ swl;
 
     const int k = g.k;
@@ -414,7 +418,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     }
     for (int e = tid; e < 2 * SP; e += kThreads) {
         const int v = e / SP, a = e % SP;
-        sm.yfold[v * SP + (a ^ M::sw(k + v))] = M::to_op((a < k) ? g.ybar[v * k + a] : 0.0f);
+        sm.yfold[v * SP + (a ^ swz(k + v))] = M::to_op((a < k) ? g.ybar[v * k + a] : 0.0f);
     }
     // rows of the second operand of Phi^T Phi: component i, or a mean at k, k+1
     const Op* grow[TC];
@@ -616,7 +620,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             if (i < KP) {
                 constexpr int half = KP >> 1;
                 const Op* prow = &sm.phi[i * SP];
-                const int psw = M::sw(i);
+                const int psw = swz(i);
                 const float* yb = &sm.ybar[v * KP + h * half];
 #pragma unroll
                 for (int a = 0; a < half; a += 8) {
@@ -774,7 +778,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 if (mt < NTK) {
                     // Phi[a][i], a = 16 mt + lane % 16, i = k0 + EPL q + e, from the
                     // component-major copy
-                    fa[ti] = M::lds_t_sw(&sm.phi[k0 * SP + mt * 16], SP, lane);
+                    fa[ti] = kPerm ? M::lds_t_sw(&sm.phi[k0 * SP + mt * 16], SP, lane)
+                                   : M::lds_t(&sm.phi[k0 * SP + mt * 16], SP, lane);
                 } else {
                     fa[ti] = M::zero_frag();
                 }
