@@ -301,9 +301,30 @@ __device__ __forceinline__ float add_xor32(float x) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// One whole run of restart r_id of the problem in g, by the calling workgroup.
-template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true>
-__device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
+template <int WR>
+__device__ __forceinline__ void wave_grid(int w, int& wr, int& wc) {
+    constexpr int WC = kWaves / WR;
+    // Waves w and w + 4 run on the same SIMD (the CU deals a workgroup's waves
+    // out to its four SIMDs in turn).  With WR >= 4 the two waves of a SIMD
+    // take the same wave row and both wave columns, so when the tile count
+    // leaves the last wave row or column short (k = 100: 7 tiles) the four
+    // SIMDs still carry near-equal shares of the MFMA work (FP32 k = 100:
+    // 44.6 -> 42.2 us per step; every tile keeps its summation order, so the
+    // results are unchanged).  The masks give the compiler the ranges of wr
+    // and wc.
+    if constexpr (WR >= 4) {
+        wr = ((w & 3) + 4 * ((w >> 2) & (WR / 4 - 1))) & (WR - 1);
+        wc = ((w >> 2) / (WR / 4)) & (WC - 1);
+    } else {
+        wr = (w / WC) & (WR - 1);
+        wc = w & (WC - 1);
+    }
+}
+
+// One whole run of restart r_id, by one wave of the calling workgroup whose
+// last tile row (DR = 1) and column (DC = 1) lie outside KP or not.
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP, int DR, int DC>
+__device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     using Op = typename M::Op;
     using Y = typename M::Y;
     constexpr int WC = kWaves / WR;
@@ -328,30 +349,21 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    // wave index in a scalar register: every tile guard below is a scalar branch
+    // wave index in a scalar register
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6) & (kWaves - 1);
-    // Waves w and w + 4 run on the same SIMD (the CU deals a workgroup's waves
-    // out to its four SIMDs in turn).  With WR >= 4 the two waves of a SIMD
-    // take the same wave row and both wave columns, so when the tile count
-    // leaves the last wave row or column short (k = 100: 7 tiles) the four
-    // SIMDs still carry near-equal shares of the MFMA work (FP32 k = 100:
-    // 44.6 -> 42.2 us per step; every tile keeps its summation order, so the
-    // results are unchanged).  The masks give the compiler the ranges of wr
-    // and wc, so tile guards that always hold for this KP fold away.
     int wr, wc;
-    if constexpr (WR >= 4) {
-        wr = ((w & 3) + 4 * ((w >> 2) & (WR / 4 - 1))) & (WR - 1);
-        wc = ((w >> 2) / (WR / 4)) & (WC - 1);
-    } else {
-        wr = (w / WC) & (WR - 1);
-        wc = w & (WC - 1);
-    }
+    wave_grid<WR>(w, wr, wc);
+    // this wave's tile rows and columns that lie inside KP (the last of each
+    // can fall outside when the tile count is not a multiple of the grid):
+    // compile-time counts, so no tile guard is left in the product loops
+    constexpr int TRL = TRK - DR, TCL = TC - DC;
     const int l16 = lane & 15, q = lane >> 4;
     // column permutation of every row 16 m + l16 of the Phi copy and the
     // exchange buffer, folded into the lane's fragment column (cq) and output
     // column (sq): k0 + cq and 16 mt + sq keep the tile offsets additive
     // (not for three staged views at KP = 96, where the extra per-lane offsets
-    // cost spills: that step measured 5.6 us plain without it, 5.9 with it)
+    // cost registers: no gain on the plain step, 6.4 -> 6.8 us per step on the
+    // compensated one)
     constexpr bool kPerm = M::EPL != 1 && !(NSTAGE == 3 && KP >= 96);
     auto swz = [](int r) { return kPerm ? M::sw(r) : 0; };
     const int swl = swz(l16);
@@ -397,7 +409,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
         for (int tj = 0; tj < TC; ++tj) {
             const int mt = wr + WR * ti, nt = wc + WC * tj;
             f32x4 v = {0.f, 0.f, 0.f, 0.f}, cv = {0.f, 0.f, 0.f, 0.f};
-            if (mt < NTK && nt < NTK) {
+            if (ti < TRL && tj < TCL) {
                 const int i = nt * 16 + l16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -424,7 +436,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const Op* grow[TC];
 #pragma unroll
     for (int tj = 0; tj < TC; ++tj) {
-        const int i = (wc + WC * tj < NTK) ? (wc + WC * tj) * 16 + l16 : 0;
+        const int i = (tj < TCL) ? (wc + WC * tj) * 16 + l16 : 0;
         grow[tj] = (mfold && (i == k || i == k + 1)) ? &sm.yfold[(i - k) * SP] : &sm.phi[i * SP];
     }
     // per-column factor of the update: 1 for a live component, 0 for padding
@@ -659,21 +671,19 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti) {
                         const int mt = wr + WR * ti;
-                        fa4[ti] = (mt < NTK) ? M::load4(&sm.phi[(mt * 16 + l16) * SP + q * KQ + s0])
+                        fa4[ti] = (ti < TRL) ? M::load4(&sm.phi[(mt * 16 + l16) * SP + q * KQ + s0])
                                              : f32x4{0.f, 0.f, 0.f, 0.f};
                     }
 #pragma unroll
-                    for (int tj = 0; tj < TC; ++tj) {
-                        const int nt = wc + WC * tj;
-                        fb4[tj] = (nt < NTK) ? M::load4(grow[tj] + q * KQ + s0) : f32x4{0.f, 0.f, 0.f, 0.f};
-                    }
+                    for (int tj = 0; tj < TC; ++tj)
+                        fb4[tj] = (tj < TCL) ? M::load4(grow[tj] + q * KQ + s0) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                             for (int tj = 0; tj < TC; ++tj)
-                                if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                                if (ti < TRL && tj < TCL)
                                     acc[ti][tj] = M::mma(fa4[ti][e], fb4[tj][e], acc[ti][tj]);
                 }
             } else {
@@ -683,18 +693,16 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + WR * ti;
-                    fa[ti] = (mt < NTK) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + (k0 + cq)]) : M::zero_frag();
+                    fa[ti] = (ti < TRL) ? M::lds(&sm.phi[(mt * 16 + l16) * SP + (k0 + cq)]) : M::zero_frag();
                 }
 #pragma unroll
-                for (int tj = 0; tj < TC; ++tj) {
-                    const int nt = wc + WC * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(grow[tj] + (k0 + cq)) : M::zero_frag();
-                }
+                for (int tj = 0; tj < TC; ++tj)
+                    fb[tj] = (tj < TCL) ? M::lds(grow[tj] + (k0 + cq)) : M::zero_frag();
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj)
-                        if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                        if (ti < TRL && tj < TCL)
                             acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
             }
             }
@@ -705,7 +713,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int mt = wr + WR * ti, nt = wc + WC * tj;
-                        if (mt >= NTK || nt >= NTK) continue;
+                        if (ti >= TRL || tj >= TCL) continue;
                         const int i = nt * 16 + l16;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -722,7 +730,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int mt = wr + WR * ti, nt = wc + WC * tj;
-                    if (mt < NTK && nt < NTK) {
+                    if (ti < TRL && tj < TCL) {
                         const int i = nt * 16 + l16;
                         const f32x4 gv = acc[ti][tj];
                         M::store4(&sm.buf[i * SB + (mt * 16 + sq)], gv * gv);
@@ -750,7 +758,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    fb4[tj] = (nt < NTK) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + kk]) : f32x4{0.f, 0.f, 0.f, 0.f};
+                    fb4[tj] = (tj < TCL) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + kk]) : f32x4{0.f, 0.f, 0.f, 0.f};
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -758,13 +766,13 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti) {
                         const int mt = wr + WR * ti;
-                        fa1[ti] = (mt < NTK && kk + e < k) ? sm.phi[(kk + e) * SP + mt * 16 + l16] : 0.0f;
+                        fa1[ti] = (ti < TRL && kk + e < k) ? sm.phi[(kk + e) * SP + mt * 16 + l16] : 0.0f;
                     }
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                         for (int tj = 0; tj < TC; ++tj)
-                            if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                            if (ti < TRL && tj < TCL)
                                 oacc[ti][tj] = M::mma(fa1[ti], fb4[tj][e], oacc[ti][tj]);
                 }
             }
@@ -775,7 +783,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti) {
                 const int mt = wr + WR * ti;
-                if (mt < NTK) {
+                if (ti < TRL) {
                     // Phi[a][i], a = 16 mt + lane % 16, i = k0 + EPL q + e, from the
                     // component-major copy
                     fa[ti] = kPerm ? M::lds_t_sw(&sm.phi[k0 * SP + mt * 16], SP, lane)
@@ -787,13 +795,13 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + WC * tj;
-                fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
+                fb[tj] = (tj < TCL) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
             }
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj)
-                    if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                    if (ti < TRL && tj < TCL)
                         oacc[ti][tj] = M::mma(fa[ti], fb[tj], oacc[ti][tj]);
         }
         }
@@ -808,7 +816,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                 const float f3 = beta * live[tj] * g.kappa;
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
-                    if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
+                    if (ti >= TRL || tj >= TCL) continue;
                     if constexpr (kComp) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) comp[ti][tj][r] = fmaf(f3, oacc[ti][tj][r], comp[ti][tj][r]);
@@ -842,8 +850,8 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
             for (int tj = 0; tj < TC; ++tj) {
                 colsum[tj] = 0.f;
                 const int i = (wc + WC * tj) * 16 + l16;
-                const float mA = (wc + WC * tj < NTK) ? sm.m[i] : 0.f;
-                const float mB = (wc + WC * tj < NTK) ? sm.m[KP + i] : 0.f;
+                const float mA = (tj < TCL) ? sm.m[i] : 0.f;
+                const float mB = (tj < TCL) ? sm.m[KP + i] : 0.f;
                 al[tj] = g.a * live[tj];
                 bmA[tj] = g.b * live[tj] * mA;
                 bmB[tj] = g.b * live[tj] * mB;
@@ -865,7 +873,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        fphi[tj] = (nt < NTK) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + (k0 + cq)])
+                        fphi[tj] = (tj < TCL) ? M::lds(&sm.phi[(nt * 16 + l16) * SP + (k0 + cq)])
                                               : M::zero_frag();
                     }
 #pragma unroll
@@ -874,7 +882,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
                         const typename M::Frag fa = M::lds(&sm.ybatch[tr * SY + k0 + q * M::EPL]);
 #pragma unroll
                         for (int tj = 0; tj < TC; ++tj)
-                            if (wc + WC * tj < NTK) pt[ti][tj] = M::mma(fa, fphi[tj], pt[ti][tj]);
+                            if (tj < TCL) pt[ti][tj] = M::mma(fa, fphi[tj], pt[ti][tj]);
                     }
                 }
                 issue_data();
@@ -885,7 +893,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        if (nt >= NTK) continue;
+                        if (tj >= TCL) continue;
                         const int i = nt * 16 + l16;
                         f32x4 qv;
 #pragma unroll
@@ -935,14 +943,14 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                         for (int tj = 0; tj < TC; ++tj) {
                             const int nt = wc + WC * tj;
-                            fp4[tj] = (nt < NTK) ? M::load4(&sm.phi[(nt * 16 + l16) * SP + kk])
+                            fp4[tj] = (tj < TCL) ? M::load4(&sm.phi[(nt * 16 + l16) * SP + kk])
                                                  : f32x4{0.f, 0.f, 0.f, 0.f};
                         }
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
 #pragma unroll
                             for (int tj = 0; tj < TC; ++tj) {
-                                if (wc + WC * tj >= NTK) continue;
+                                if (tj >= TCL) continue;
                                 pa[tj] = M::mma(fa4[e], fp4[tj][e], pa[tj]);
                                 if constexpr (NSTAGE != 1) pb[tj] = M::mma(fb4[e], fp4[tj][e], pb[tj]);
                             }
@@ -961,7 +969,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        if (nt < NTK) {
+                        if (tj < TCL) {
                             const typename M::Frag fphi = M::lds(&sm.phi[(nt * 16 + l16) * SP + (k0 + cq)]);
                             pa[tj] = M::mma(fa, fphi, pa[tj]);
                             if constexpr (NSTAGE != 1) pb[tj] = M::mma(fbv, fphi, pb[tj]);
@@ -972,7 +980,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    if (nt >= NTK) continue;
+                    if (tj >= TCL) continue;
                     const int i = nt * 16 + l16;
                     f32x4 qv;
 #pragma unroll
@@ -994,7 +1002,7 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + WC * tj;
-                if (nt >= NTK) continue;
+                if (tj >= TCL) continue;
                 colsum[tj] = add_xor16(colsum[tj]);
                 colsum[tj] = add_xor32(colsum[tj]);
                 if (q == 0) sm.s[wr * KP + nt * 16 + l16] = colsum[tj];
@@ -1031,7 +1039,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
                         const int nt = wc + WC * tj;
-                        fb4[tj] = (nt < NTK) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + tt]) : f32x4{0.f, 0.f, 0.f, 0.f};
+                        fb4[tj] = (tj < TCL) ? M::load4(&sm.buf[(nt * 16 + l16) * SB + tt]) : f32x4{0.f, 0.f, 0.f, 0.f};
                     }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
@@ -1041,7 +1049,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                         for (int ti = 0; ti < TRK; ++ti) {
                             const int mt = wr + WR * ti;
                             const int a = mt * 16 + l16;
-                            if (mt >= NTK) {
+                            if (ti >= TRL) {
                                 fa1[ti] = 0.0f;
                             } else if constexpr (NSTAGE > 0) {
                                 fa1[ti] = sm.ybatch[(vc * MB + tr) * SY + a];
@@ -1053,7 +1061,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                         for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                             for (int tj = 0; tj < TC; ++tj)
-                                if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                                if (ti < TRL && tj < TCL)
                                     dacc[ti][tj] = M::mma(fa1[ti], fb4[tj][e], dacc[ti][tj]);
                     }
                 }
@@ -1065,7 +1073,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                 for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + WR * ti;
                     const int a = mt * 16 + l16;
-                    if (mt >= NTK) {
+                    if (ti >= TRL) {
                         fa[ti] = M::zero_frag();
                     } else if constexpr (NSTAGE > 0) {
                         // EPL rows t = k0 + EPL*q + e of column a of the staged batch
@@ -1084,13 +1092,13 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                 for (int tj = 0; tj < TC; ++tj) {
                     const int nt = wc + WC * tj;
-                    fb[tj] = (nt < NTK) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
+                    fb[tj] = (tj < TCL) ? M::lds(&sm.buf[(nt * 16 + l16) * SB + (k0 + cq)]) : M::zero_frag();
                 }
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj)
-                        if (wr + WR * ti < NTK && wc + WC * tj < NTK)
+                        if (ti < TRL && tj < TCL)
                             dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
             }
             }
@@ -1098,7 +1106,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
             for (int tj = 0; tj < TC; ++tj) {
                 const int nt = wc + WC * tj;
-                if (nt >= NTK) continue;
+                if (tj >= TCL) continue;
                 const int i = nt * 16 + l16;
                 float ssum = 0.f;
 #pragma unroll
@@ -1109,7 +1117,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti) {
                         const int mt = wr + WR * ti;
-                        if (mt >= NTK) continue;
+                        if (ti >= TRL) continue;
                         const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
                         const f32x4 pv = phi_get(ti, tj);
 #pragma unroll
@@ -1125,7 +1133,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
                     const int mt = wr + WR * ti;
-                    if (mt >= NTK) continue;
+                    if (ti >= TRL) continue;
                     const f32x4 ybc = *reinterpret_cast<const f32x4*>(&sm.ybar[2 * KP + mt * 16 + 4 * q]);
                     f32x4 v = phi_get(ti, tj);
                     if constexpr (kComp) {
@@ -1154,7 +1162,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                 for (int tj = 0; tj < TC; ++tj)
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti) {
-                        if (wr + WR * ti >= NTK || wc + WC * tj >= NTK) continue;
+                        if (ti >= TRL || tj >= TCL) continue;
                         const f32x4 pv = phi_get(ti, tj);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) bad |= !isfinite(pv[r]);
@@ -1166,7 +1174,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
                     for (int ti = 0; ti < TRK; ++ti) {
                         const int mt = wr + WR * ti, nt = wc + WC * tj;
-                        if (mt >= NTK || nt >= NTK) continue;
+                        if (ti >= TRL || tj >= TCL) continue;
                         const int i = nt * 16 + l16;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -1222,7 +1230,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 #pragma unroll
         for (int tj = 0; tj < TC; ++tj) {
             const int mt = wr + WR * ti, nt = wc + WC * tj;
-            if (mt >= NTK || nt >= NTK) continue;
+            if (ti >= TRL || tj >= TCL) continue;
             const int i = nt * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -1240,6 +1248,39 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
     if (bad && g.nonfinite) *g.nonfinite = 1;
 }
 
+
+// One whole run of restart r_id of the problem in g, by the calling workgroup:
+// each wave runs the body specialised for how many of its tile rows and
+// columns lie inside KP, so no tile guard is left inside the product loops
+// (with the guards as run-time branches, FP32 KP = 112 spilled 64 bytes per
+// lane and took 41.5 us per k = 100 step against 39.3; BF16 KP = 96 with
+// three views 5.54 against 4.97 us).  Every result is the same bit for bit.
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true>
+__device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
+    constexpr int WC = kWaves / WR, NTK = KP / 16;
+    constexpr int TC = (NTK + WC - 1) / WC, TRK = (NTK + WR - 1) / WR;
+    constexpr bool kCanDR = WR * (TRK - 1) + (WR - 1) >= NTK;   // some wave's last tile row lies outside
+    constexpr bool kCanDC = WC * (TC - 1) + (WC - 1) >= NTK;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & (kWaves - 1);
+    int wr, wc;
+    wave_grid<WR>(w, wr, wc);
+    const bool dr = kCanDR && wr + WR * (TRK - 1) >= NTK;
+    const bool dc = kCanDC && wc + WC * (TC - 1) >= NTK;
+    if constexpr (kCanDR && kCanDC) {
+        if (dr && dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 1>(g, r_id, sm);
+        else if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 0>(g, r_id, sm);
+        else if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 1>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+    } else if constexpr (kCanDR) {
+        if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 0>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+    } else if constexpr (kCanDC) {
+        if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 1>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+    } else {
+        sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+    }
+}
 
 // Host: the scalar part of the arguments shared by every entry point.  The
 // pointers are set by the caller.  Returns OTM_OK or a status with a message.
