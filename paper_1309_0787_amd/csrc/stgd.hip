@@ -4,16 +4,25 @@
 namespace otm {
 namespace {
 
-template <class M, int KP, int NSTAGE, bool COMP>
+template <class M, int KP, int NSTAGE, bool COMP, int NTL>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     __shared__ __attribute__((aligned(16))) SgdSmem<M, KP, NSTAGE, 4> sm;
-    sgd_body<M, KP, NSTAGE, 4, false, COMP>(g, blockIdx.x, sm);
+    sgd_body<M, KP, NSTAGE, 4, false, COMP, NTL>(g, blockIdx.x, sm);
 }
 
 template <class M, int KP, int NSTAGE, bool COMP>
 int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
     static_assert(smem_bytes<M, KP, NSTAGE>() <= kLdsLimit, "STGD shared memory exceeds 160 KB");
-    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP>), dim3(restarts), dim3(kThreads), 0, st, a);
+    // BF16 pads k to a multiple of 32: when k + 2 (the components and the two
+    // folded means) fits in one tile less than KP, the last tile row and
+    // column of every k x k product hold only padding and are skipped
+    if constexpr (M::EPL == 8) {
+        if (a.k + 2 <= KP - 16) {
+            hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16 - 1>), dim3(restarts), dim3(kThreads), 0, st, a);
+            return check_launch("sgd_kernel");
+        }
+    }
+    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16>), dim3(restarts), dim3(kThreads), 0, st, a);
     return check_launch("sgd_kernel");
 }
 

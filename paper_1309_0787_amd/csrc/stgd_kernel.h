@@ -322,8 +322,10 @@ __device__ __forceinline__ void wave_grid(int w, int& wr, int& wc) {
 }
 
 // One whole run of restart r_id, by one wave of the calling workgroup whose
-// last tile row (DR = 1) and column (DC = 1) lie outside KP or not.
-template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP, int DR, int DC>
+// last tile row (DR = 1) and column (DC = 1) it skips or not: they lie
+// outside KP, or past the NTL tiles that hold components, coordinates and
+// the two folded means (the rest is padding, zero in every product).
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP, int NTL, int DR, int DC>
 __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     using Op = typename M::Op;
     using Y = typename M::Y;
@@ -353,9 +355,10 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6) & (kWaves - 1);
     int wr, wc;
     wave_grid<WR>(w, wr, wc);
-    // this wave's tile rows and columns that lie inside KP (the last of each
-    // can fall outside when the tile count is not a multiple of the grid):
-    // compile-time counts, so no tile guard is left in the product loops
+    // this wave's tile rows and columns that it computes (the last of each can
+    // fall outside KP when the tile count is not a multiple of the grid, or
+    // hold only padding): compile-time counts, so no tile guard is left in
+    // the product loops
     constexpr int TRL = TRK - DR, TCL = TC - DC;
     const int l16 = lane & 15, q = lane >> 4;
     // column permutation of every row 16 m + l16 of the Phi copy and the
@@ -409,7 +412,7 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
         for (int tj = 0; tj < TC; ++tj) {
             const int mt = wr + WR * ti, nt = wc + WC * tj;
             f32x4 v = {0.f, 0.f, 0.f, 0.f}, cv = {0.f, 0.f, 0.f, 0.f};
-            if (ti < TRL && tj < TCL) {
+            if (mt < NTK && nt < NTK) {   // every tile inside KP, the skipped padding tiles as zeros
                 const int i = nt * 16 + l16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -424,6 +427,9 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
             if constexpr (kPhiReg) phi_r[ti][tj] = v;
             if constexpr (kComp) comp[ti][tj] = cv;
         }
+    if constexpr (NTL < NTK) {   // regions of skipped tiles are never written: zero once
+        for (int e = tid; e < KP * SB; e += kThreads) sm.buf[e] = M::to_op(0.0f);
+    }
     for (int e = tid; e < 3 * KP; e += kThreads) {
         const int v = e / KP, a = e % KP;
         sm.ybar[e] = (a < k) ? g.ybar[v * k + a] : 0.0f;
@@ -1251,34 +1257,38 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 
 // One whole run of restart r_id of the problem in g, by the calling workgroup:
 // each wave runs the body specialised for how many of its tile rows and
-// columns lie inside KP, so no tile guard is left inside the product loops
+// columns it computes, so no tile guard is left inside the product loops
 // (with the guards as run-time branches, FP32 KP = 112 spilled 64 bytes per
 // lane and took 41.5 us per k = 100 step against 39.3; BF16 KP = 96 with
-// three views 5.54 against 4.97 us).  Every result is the same bit for bit.
-template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true>
+// three views 5.54 against 4.97 us).  NTL < KP / 16 (BF16, when k + 2 fits
+// in fewer tiles than KP holds) also drops the tiles that hold only padding:
+// BF16 k = 100 at KP = 128 computes 7 x 7 output tiles per product instead
+// of 8 x 8 (4.80 -> 4.23 us per step).  Every result is the same bit for bit.
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true, int NTL = KP / 16>
 __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     constexpr int WC = kWaves / WR, NTK = KP / 16;
     constexpr int TC = (NTK + WC - 1) / WC, TRK = (NTK + WR - 1) / WR;
-    constexpr bool kCanDR = WR * (TRK - 1) + (WR - 1) >= NTK;   // some wave's last tile row lies outside
-    constexpr bool kCanDC = WC * (TC - 1) + (WC - 1) >= NTK;
+    static_assert(NTL >= 1 && NTL <= NTK, "live tiles within KP");
+    constexpr bool kCanDR = WR * (TRK - 1) + (WR - 1) >= NTL;   // some wave's last tile row lies outside
+    constexpr bool kCanDC = WC * (TC - 1) + (WC - 1) >= NTL;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & (kWaves - 1);
     int wr, wc;
     wave_grid<WR>(w, wr, wc);
-    const bool dr = kCanDR && wr + WR * (TRK - 1) >= NTK;
-    const bool dc = kCanDC && wc + WC * (TC - 1) >= NTK;
+    const bool dr = kCanDR && wr + WR * (TRK - 1) >= NTL;
+    const bool dc = kCanDC && wc + WC * (TC - 1) >= NTL;
     if constexpr (kCanDR && kCanDC) {
-        if (dr && dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 1>(g, r_id, sm);
-        else if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 0>(g, r_id, sm);
-        else if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 1>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+        if (dr && dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 1>(g, r_id, sm);
+        else if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0>(g, r_id, sm);
+        else if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
     } else if constexpr (kCanDR) {
-        if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 1, 0>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+        if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
     } else if constexpr (kCanDC) {
-        if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 1>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+        if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
     } else {
-        sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, 0, 0>(g, r_id, sm);
+        sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
     }
 }
 
