@@ -80,6 +80,34 @@ def test_step_bf16(k, alpha0, compensated):
     assert rel(phi_cols(P) - Phi0, ref - Phi0) < 3e-2
 
 
+@pytest.mark.parametrize("k", [14, 15, 46, 47, 78, 79, 110, 111])
+@pytest.mark.parametrize("three", [False, True])
+@pytest.mark.parametrize("compensated", [True, False])
+def test_step_bf16_padding_tiles(k, three, compensated):
+    """BF16 pads k to a multiple of 32; when k + 2 (components and the two
+    folded means) fits in one 16-wide tile less, the products skip the last
+    tile row and column.  k on both sides of each threshold, one shared view
+    (staged rows, plain or compensated update) and three views."""
+    rows = 100
+    YA, YB, YC, ybar, Phi0 = _inputs(rows, k, seed=k + 11, three=three)
+    YA, YB, YC = (bf16_round(x) for x in (YA, YB, YC))
+    if not three:
+        YB = YC = YA
+    ybar, Phi0 = f32_round(ybar), f32_round(Phi0)
+    beta = 0.01
+    ref = oracle.sgd_step(YA, YB, YC, ybar, Phi0, beta, 0.5)
+    if three:
+        A, B, C = _dev_views(YA, YB, YC, k, otm.BF16)
+    else:
+        A, _, _ = _dev_views(YA, YA, YA, k, otm.BF16)
+        B = C = A
+    P = phi_rows(Phi0)
+    p = otm.SgdParams(k=k, batch=100, alpha0=0.5, y_dtype=otm.BF16, compensated=compensated)
+    otm.sgd_step(p, rows, A, B, C, to_dev(ybar), beta, P)
+    torch.cuda.synchronize()
+    assert rel(phi_cols(P) - Phi0, ref - Phi0) < 3e-2
+
+
 def test_step_aliased_views_theta():
     k, rows = 20, 50
     YA, _, _, ybar, Phi0 = _inputs(rows, k, seed=3, three=False)
