@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void sgd_persistent_kernel(const BatchJob
         __syncthreads();   // s_job is rewritten only after every wave has read it
         if (j >= count) break;
         const SgdArgs g = jobs[j].args;
-        sgd_body<MmaF32, KP, VV::NS, VV::WR, true>(g, jobs[j].r_id, sm);
+        sgd_body<MmaF32, KP, VV::NS, VV::WR, true, true, KP / 16, V3 == 0 && VV::NS == 0>(g, jobs[j].r_id, sm);
     }
 }
 

@@ -4,26 +4,36 @@
 namespace otm {
 namespace {
 
-template <class M, int KP, int NSTAGE, bool COMP, int NTL>
+template <class M, int KP, int NSTAGE, bool COMP, int NTL, bool OV>
 __global__ __launch_bounds__(kThreads) void sgd_kernel(SgdArgs g) {
     __shared__ __attribute__((aligned(16))) SgdSmem<M, KP, NSTAGE, 4> sm;
-    sgd_body<M, KP, NSTAGE, 4, false, COMP, NTL>(g, blockIdx.x, sm);
+    sgd_body<M, KP, NSTAGE, 4, false, COMP, NTL, OV>(g, blockIdx.x, sm);
 }
 
-template <class M, int KP, int NSTAGE, bool COMP>
-int launch_sgd(const SgdArgs& a, int restarts, hipStream_t st) {
-    static_assert(smem_bytes<M, KP, NSTAGE>() <= kLdsLimit, "STGD shared memory exceeds 160 KB");
+template <class M, int KP, int NSTAGE, bool COMP, bool OV>
+int launch_sgd_v(const SgdArgs& a, int restarts, hipStream_t st) {
     // BF16 pads k to a multiple of 32: when k + 2 (the components and the two
     // folded means) fits in one tile less than KP, the last tile row and
     // column of every k x k product hold only padding and are skipped
     if constexpr (M::EPL == 8) {
         if (a.k + 2 <= KP - 16) {
-            hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16 - 1>), dim3(restarts), dim3(kThreads), 0, st, a);
+            hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16 - 1, OV>), dim3(restarts), dim3(kThreads), 0, st, a);
             return check_launch("sgd_kernel");
         }
     }
-    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16>), dim3(restarts), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((sgd_kernel<M, KP, NSTAGE, COMP, KP / 16, OV>), dim3(restarts), dim3(kThreads), 0, st, a);
     return check_launch("sgd_kernel");
+}
+
+// Rows read from global memory (no staging) with the three views aliased:
+// the body computes the batch product once (P_B = P_A)
+template <class M, int KP, int NSTAGE, bool COMP>
+int launch_sgd(const SgdArgs& a, int restarts, bool aliased, hipStream_t st) {
+    static_assert(smem_bytes<M, KP, NSTAGE>() <= kLdsLimit, "STGD shared memory exceeds 160 KB");
+    if constexpr (NSTAGE == 0) {
+        if (aliased) return launch_sgd_v<M, KP, NSTAGE, COMP, true>(a, restarts, st);
+    }
+    return launch_sgd_v<M, KP, NSTAGE, COMP, false>(a, restarts, st);
 }
 
 // Picks the instantiation: the smallest padded k, then the largest batch
@@ -35,9 +45,9 @@ int dispatch_staging(const SgdArgs& a, int restarts, bool aliased, hipStream_t s
     constexpr int s1 = staging_for<M, KP>(true), s3 = staging_for<M, KP>(false);
     if constexpr (M::EPL != 1) {
         if (!a.compensated)
-            return aliased ? launch_sgd<M, KP, s1, false>(a, restarts, st) : launch_sgd<M, KP, s3, false>(a, restarts, st);
+            return aliased ? launch_sgd<M, KP, s1, false>(a, restarts, true, st) : launch_sgd<M, KP, s3, false>(a, restarts, false, st);
     }
-    return aliased ? launch_sgd<M, KP, s1, true>(a, restarts, st) : launch_sgd<M, KP, s3, true>(a, restarts, st);
+    return aliased ? launch_sgd<M, KP, s1, true>(a, restarts, true, st) : launch_sgd<M, KP, s3, true>(a, restarts, false, st);
 }
 
 int run_common(const otm_sgd_params* p, int32_t n, const void* YA, const void* YB, const void* YC,

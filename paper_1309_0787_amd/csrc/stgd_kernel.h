@@ -324,8 +324,9 @@ __device__ __forceinline__ void wave_grid(int w, int& wr, int& wc) {
 // One whole run of restart r_id, by one wave of the calling workgroup whose
 // last tile row (DR = 1) and column (DC = 1) it skips or not: they lie
 // outside KP, or past the NTL tiles that hold components, coordinates and
-// the two folded means (the rest is padding, zero in every product).
-template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP, int NTL, int DR, int DC>
+// the two folded means (the rest is padding, zero in every product).  OV:
+// the three views alias and the rows are read from global memory.
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP, int NTL, int DR, int DC, bool OV>
 __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     using Op = typename M::Op;
     using Y = typename M::Y;
@@ -940,7 +941,7 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                         f32x4 fa4, fb4 = {0.f, 0.f, 0.f, 0.f};
                         if constexpr (NSTAGE == 0) {
                             fa4 = yrow4(rowA, kk, k);
-                            fb4 = yrow4(rowB, kk, k);
+                            if constexpr (!OV) fb4 = yrow4(rowB, kk, k);
                         } else {
                             fa4 = M::load4(sA + kk);
                             if constexpr (NSTAGE == 3) fb4 = M::load4(sB + kk);
@@ -958,7 +959,7 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                             for (int tj = 0; tj < TC; ++tj) {
                                 if (tj >= TCL) continue;
                                 pa[tj] = M::mma(fa4[e], fp4[tj][e], pa[tj]);
-                                if constexpr (NSTAGE != 1) pb[tj] = M::mma(fb4[e], fp4[tj][e], pb[tj]);
+                                if constexpr (NSTAGE != 1 && !OV) pb[tj] = M::mma(fb4[e], fp4[tj][e], pb[tj]);
                             }
                     }
                 } else {
@@ -996,7 +997,7 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                             colsum[tj] = fmaf(xa, xa, colsum[tj]);
                             qv[r] = xa * fmaf(al[tj], xa, -(bmA[tj] + bmB[tj]));
                         } else {
-                            const float xb = pb[tj][r];
+                            const float xb = OV ? xa : pb[tj][r];   // one view: P_B = P_A
                             colsum[tj] = fmaf(xa, xb, colsum[tj]);
                             qv[r] = fmaf(xa, fmaf(al[tj], xb, -bmB[tj]), -bmA[tj] * xb);
                         }
@@ -1263,8 +1264,11 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
 // three views 5.54 against 4.97 us).  NTL < KP / 16 (BF16, when k + 2 fits
 // in fewer tiles than KP holds) also drops the tiles that hold only padding:
 // BF16 k = 100 at KP = 128 computes 7 x 7 output tiles per product instead
-// of 8 x 8 (4.80 -> 4.23 us per step).  Every result is the same bit for bit.
-template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true, int NTL = KP / 16>
+// of 8 x 8 (4.80 -> 4.23 us per step).  OV (one view, rows read from global
+// memory) computes the batch product once, since P_B = P_A (FP32 k = 100:
+// 39.1 -> 32.9 us per step; k = 128: 48.8 -> 40.5).  Every result is the
+// same bit for bit.
+template <class M, int KP, int NSTAGE, int WR, bool SCORE, bool COMP = true, int NTL = KP / 16, bool OV = false>
 __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSmem<M, KP, NSTAGE, WR>& sm) {
     constexpr int WC = kWaves / WR, NTK = KP / 16;
     constexpr int TC = (NTK + WC - 1) / WC, TRK = (NTK + WR - 1) / WR;
@@ -1277,18 +1281,18 @@ __device__ __forceinline__ void sgd_body(const SgdArgs& g, const int r_id, SgdSm
     const bool dr = kCanDR && wr + WR * (TRK - 1) >= NTL;
     const bool dc = kCanDC && wc + WC * (TC - 1) >= NTL;
     if constexpr (kCanDR && kCanDC) {
-        if (dr && dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 1>(g, r_id, sm);
-        else if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0>(g, r_id, sm);
-        else if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
+        if (dr && dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 1, OV>(g, r_id, sm);
+        else if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0, OV>(g, r_id, sm);
+        else if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1, OV>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0, OV>(g, r_id, sm);
     } else if constexpr (kCanDR) {
-        if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
+        if (dr) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 1, 0, OV>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0, OV>(g, r_id, sm);
     } else if constexpr (kCanDC) {
-        if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1>(g, r_id, sm);
-        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
+        if (dc) sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 1, OV>(g, r_id, sm);
+        else sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0, OV>(g, r_id, sm);
     } else {
-        sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0>(g, r_id, sm);
+        sgd_body_t<M, KP, NSTAGE, WR, SCORE, COMP, NTL, 0, 0, OV>(g, r_id, sm);
     }
 }
 
