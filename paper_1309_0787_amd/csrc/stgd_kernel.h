@@ -346,9 +346,6 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     // MFMA then starts from zero without clearing registers); FP32 and
     // unstaged rows spill registers beyond 2
     constexpr int UNR_P = (M::EPL == 8 && NSTAGE > 0) ? 4 : 2;
-    // FP32 without staging: the D product reads its rows from L2 inside the
-    // loop, so more of its iterations are kept in flight
-    constexpr int UNR_D = (NSTAGE == 0 && M::EPL == 1) ? 4 : UNR;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1073,8 +1070,7 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     }
                 }
             } else {
-#pragma unroll UNR_D
-            for (int k0 = 0; k0 < MB; k0 += M::KI) {
+            auto dstep = [&](const int k0) {
                 typename M::Frag fa[TRK], fb[TC];
 #pragma unroll
                 for (int ti = 0; ti < TRK; ++ti) {
@@ -1107,6 +1103,17 @@ if constexpr (M::EPL == 1 && NSTAGE > 0) {
                     for (int tj = 0; tj < TC; ++tj)
                         if (ti < TRL && tj < TCL)
                             dacc[ti][tj] = M::mma(fa[ti], fb[tj], dacc[ti][tj]);
+            };
+            if constexpr (M::EPL == 1 && NSTAGE == 0) {
+                // FP32 rows read from global memory: the batch rows past the batch
+                // size are zero, so the contraction stops at the first multiple of
+                // KI past them (the products it skips add exact zeros; FP32 k = 100
+                // 32.9 -> 31.7 us per step)
+                const int dlim = (nb + M::KI - 1) / M::KI * M::KI;
+                for (int k0 = 0; k0 < dlim; k0 += M::KI) dstep(k0);
+            } else {
+#pragma unroll UNR
+                for (int k0 = 0; k0 < MB; k0 += M::KI) dstep(k0);
             }
             }
             const float invB = 1.0f / static_cast<float>(nb);
