@@ -39,8 +39,9 @@
 // set of products in another order.
 //
 // Four workgroup barriers per step: after G*G, after O (the buffer then
-// takes Q), after Q, after the update.  The batch is padded to 128 rows in
-// every product, so every tile loop has a compile-time trip count.
+// takes Q), after Q, after the update.  The batch is padded to 128 rows, so
+// every tile loop has a compile-time trip count (the FP32 D product over rows
+// read from global memory stops at the batch size instead).
 //
 // Optional scoring pass (score != NULL): after the last update, one more pass
 // over the rows in natural order evaluates, without updating,
