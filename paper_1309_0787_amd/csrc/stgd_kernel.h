@@ -53,6 +53,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "otm_internal.h"
 
@@ -302,6 +303,18 @@ __device__ __forceinline__ float add_xor32(float x) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// Symmetric G = Phi^T Phi with 8 tile rows on a 4 x 2 wave grid: wave row wr
+// takes tile rows wr and 7 - wr (tile row ti = 0, 1) and, of the tile columns
+// wc + 2 tj, only those on or above the diagonal and inside the ntl live tiles.
+// Each wave row then carries 7 (ntl = 7) or 9 (ntl = 8) tiles.
+__host__ __device__ constexpr int tri_row(int wr, int ti) { return ti == 0 ? wr : 7 - wr; }
+__host__ __device__ constexpr bool tri_tile(int wr, int wc, int ti, int tj, int ntl) {
+    return tri_row(wr, ti) <= wc + 2 * tj && wc + 2 * tj < ntl;
+}
+
+template <int N>
+using IntC = std::integral_constant<int, N>;
+
 template <int WR>
 __device__ __forceinline__ void wave_grid(int w, int& wr, int& wc) {
     constexpr int WC = kWaves / WR;
@@ -368,6 +381,14 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     // compensated one)
     constexpr bool kPerm = M::EPL != 1 && !(NSTAGE == 3 && KP >= 96);
     auto swz = [](int r) { return kPerm ? M::sw(r) : 0; };
+    // BF16 at KP = 128: the G product computes only the tiles of tri_tile and
+    // writes the others from them (G is symmetric on the components, and the
+    // matrix cores sum Phi_i^T Phi_j and Phi_j^T Phi_i in the same order, so
+    // the results are unchanged).  Only in the plain one-view kernel with 7
+    // live tiles (k = 100: 4.28-4.37 -> 4.14 us per step); with 8 live tiles
+    // or with compensation terms the extra registers spill and the step is
+    // slower, so those keep the full product.
+    constexpr bool kTri = M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE == 1 && !COMP && NTL == 7 && !SCORE;
     const int swl = swz(l16);
     const int cq = (q * M::EPL) ^ swl, sq = (4 * q) ^ swl;
 
@@ -660,7 +681,92 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
             acc = add_xor1(acc);
             if (h == 0 && i < KP) sm.m[v * KP + i] = acc;
         }
-        {
+        if constexpr (kTri) {
+            // one straight-line body per wave position: the tiles, the fragment
+            // loads and the stores are all fixed at compile time
+            auto gtri = [&](auto wrc, auto wcc) {
+                constexpr int A = decltype(wrc)::value, C = decltype(wcc)::value;
+                f32x4 acc[2][TC];
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k0 = 0; k0 < KP; k0 += M::KI) {
+                    typename M::Frag fa[2], fb[TC];
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti) {
+                        bool need = false;
+#pragma unroll
+                        for (int tj = 0; tj < TC; ++tj) need = need || tri_tile(A, C, ti, tj, NTL);
+                        fa[ti] = need ? M::lds(&sm.phi[(tri_row(A, ti) * 16 + l16) * SP + (k0 + cq)])
+                                      : M::zero_frag();
+                    }
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj)
+                        fb[tj] = (tri_tile(A, C, 0, tj, NTL) || tri_tile(A, C, 1, tj, NTL))
+                                     ? M::lds(grow[tj] + (k0 + cq)) : M::zero_frag();
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < TC; ++tj)
+                            if (tri_tile(A, C, ti, tj, NTL)) acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
+                }
+                if constexpr (!kComp) commit(nb);
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj) {
+                        if (!tri_tile(A, C, ti, tj, NTL)) continue;
+                        const int mt = tri_row(A, ti), nt = C + 2 * tj;
+                        const int i = nt * 16 + l16;
+                        const f32x4 gv = acc[ti][tj];
+                        const f32x4 g2 = gv * gv;
+                        M::store4(&sm.buf[i * SB + (mt * 16 + sq)], g2);
+                        if (mfold && (i == k || i == k + 1))
+                            *reinterpret_cast<f32x4*>(&sm.m[(i - k) * KP + mt * 16 + 4 * q]) = gv;
+                        if (mt < nt) {
+                            // the transposed tile: lanes 2m and 2m + 1 (columns 2m, 2m + 1)
+                            // swap halves so that the even lane holds rows 4q, 4q + 1 and
+                            // the odd one rows 4q + 2, 4q + 3 of both columns, each row
+                            // pair one 4-byte store.  Its entries in the padding columns
+                            // k, k + 1 (mA^2, mB^2, where the other tile has zeros) meet
+                            // the zero rows k, k + 1 of Phi in O.
+                            const bool odd = l16 & 1;
+                            const float x0 = odd ? g2[0] : g2[2], x1 = odd ? g2[1] : g2[3];
+                            const float y0 =
+                                __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x0), 0xB1, 0xF, 0xF, false));
+                            const float y1 =
+                                __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x1), 0xB1, 0xF, 0xF, false));
+                            bf16x2 r0, r1;
+                            r0[0] = M::to_op(odd ? y0 : g2[0]);
+                            r0[1] = M::to_op(odd ? g2[2] : y0);
+                            r1[0] = M::to_op(odd ? y1 : g2[1]);
+                            r1[1] = M::to_op(odd ? g2[3] : y1);
+                            const int j0 = mt * 16 + 4 * q + (odd ? 2 : 0);
+                            const int c = (nt * 16 + (l16 & ~1)) ^ swz(j0);   // row j0 + 1: same permutation
+                            *reinterpret_cast<bf16x2*>(&sm.buf[j0 * SB + c]) = r0;
+                            *reinterpret_cast<bf16x2*>(&sm.buf[(j0 + 1) * SB + c]) = r1;
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+            };
+            // only the wave positions that reach this body (DR, DC) are instantiated
+            const int pos = wr * 2 + wc;
+            auto at = [&](auto wrc, auto wcc) {
+                constexpr int A = decltype(wrc)::value, C = decltype(wcc)::value;
+                if constexpr (((A + WR * (TRK - 1) >= NTL) == (DR == 1)) && ((C + WC * (TC - 1) >= NTL) == (DC == 1)))
+                    if (pos == A * 2 + C) gtri(wrc, wcc);
+            };
+            at(IntC<0>{}, IntC<0>{});
+            at(IntC<0>{}, IntC<1>{});
+            at(IntC<1>{}, IntC<0>{});
+            at(IntC<1>{}, IntC<1>{});
+            at(IntC<2>{}, IntC<0>{});
+            at(IntC<2>{}, IntC<1>{});
+            at(IntC<3>{}, IntC<0>{});
+            at(IntC<3>{}, IntC<1>{});
+        } else {
             f32x4 acc[TRK][TC];
 #pragma unroll
             for (int ti = 0; ti < TRK; ++ti)
