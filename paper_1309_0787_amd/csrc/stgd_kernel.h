@@ -384,11 +384,12 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     // BF16 at KP = 128: the G product computes only the tiles of tri_tile and
     // writes the others from them (G is symmetric on the components, and the
     // matrix cores sum Phi_i^T Phi_j and Phi_j^T Phi_i in the same order, so
-    // the results are unchanged).  Only in the plain one-view kernel with 7
-    // live tiles (k = 100: 4.28-4.37 -> 4.14 us per step); with 8 live tiles
-    // or with compensation terms the extra registers spill and the step is
-    // slower, so those keep the full product.
-    constexpr bool kTri = M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE == 1 && !COMP && NTL == 7 && !SCORE;
+    // the results are unchanged).  Only in the plain kernels with 7 live
+    // tiles and at most one staged view (k = 100, one view: 4.28-4.37 -> 4.14
+    // us per step; three views read from global memory: 16.7-16.9 -> 16.4);
+    // with 8 live tiles or with compensation terms the extra registers spill
+    // and the step is slower, so those keep the full product.
+    constexpr bool kTri = M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE <= 1 && !COMP && NTL == 7 && !SCORE;
     const int swl = swz(l16);
     const int cq = (q * M::EPL) ^ swl, sq = (4 * q) ^ swl;
 
