@@ -303,13 +303,15 @@ __device__ __forceinline__ float add_xor32(float x) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Symmetric G = Phi^T Phi with 8 tile rows on a 4 x 2 wave grid: wave row wr
-// takes tile rows wr and 7 - wr (tile row ti = 0, 1) and, of the tile columns
-// wc + 2 tj, only those on or above the diagonal and inside the ntl live tiles.
-// Each wave row then carries 7 (ntl = 7) or 9 (ntl = 8) tiles.
-__host__ __device__ constexpr int tri_row(int wr, int ti) { return ti == 0 ? wr : 7 - wr; }
-__host__ __device__ constexpr bool tri_tile(int wr, int wc, int ti, int tj, int ntl) {
-    return tri_row(wr, ti) <= wc + 2 * tj && wc + 2 * tj < ntl;
+// Symmetric G = Phi^T Phi with ntk = 7 or 8 tile rows on a 4 x 2 wave grid:
+// wave row wr takes tile rows wr and ntk - 1 - wr (tile row ti = 0, 1; the
+// second only where it differs from the first) and, of the tile columns
+// wc + 2 tj, only those on or above the diagonal and inside the ntl live
+// tiles.  A wave row then carries at most 7 (ntl = 7, ntk = 8), 8 (ntk = 7)
+// or 9 (ntl = 8) tiles.
+__host__ __device__ constexpr int tri_row(int wr, int ti, int ntk) { return ti == 0 ? wr : ntk - 1 - wr; }
+__host__ __device__ constexpr bool tri_tile(int wr, int wc, int ti, int tj, int ntl, int ntk) {
+    return (ti == 0 || ntk - 1 - wr > wr) && tri_row(wr, ti, ntk) <= wc + 2 * tj && wc + 2 * tj < ntl;
 }
 
 template <int N>
@@ -384,12 +386,16 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     // BF16 at KP = 128: the G product computes only the tiles of tri_tile and
     // writes the others from them (G is symmetric on the components, and the
     // matrix cores sum Phi_i^T Phi_j and Phi_j^T Phi_i in the same order, so
-    // the results are unchanged).  Only in the plain kernels with 7 live
+    // the results are unchanged).  BF16: only in the plain kernels with 7 live
     // tiles and at most one staged view (k = 100, one view: 4.28-4.37 -> 4.14
     // us per step; three views read from global memory: 16.7-16.9 -> 16.4);
     // with 8 live tiles or with compensation terms the extra registers spill
-    // and the step is slower, so those keep the full product.
-    constexpr bool kTri = M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE <= 1 && !COMP && NTL == 7 && !SCORE;
+    // and the step is slower, so those keep the full product.  FP32: the
+    // single-run kernels whose rows are read from global memory (k = 100, one
+    // view: 31.3-31.6 -> 28.8-29.0 us; k = 128: 39.0 -> 35.8 us); the batched
+    // kernels, which also score restarts from G, keep the full product.
+    constexpr bool kTri = (M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE <= 1 && !COMP && NTL == 7 && !SCORE) ||
+                          (M::EPL == 1 && WR == 4 && (KP == 112 || KP == 128) && NSTAGE == 0 && !SCORE);
     const int swl = swz(l16);
     const int cq = (q * M::EPL) ^ swl, sq = (4 * q) ^ swl;
 
@@ -692,6 +698,32 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                 for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
+if constexpr (M::EPL == 1) {
+#pragma unroll 1
+                for (int s0 = 0; s0 < KQ; s0 += 4) {
+                    f32x4 fa4[2], fb4[TC];
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti) {
+                        bool need = false;
+#pragma unroll
+                        for (int tj = 0; tj < TC; ++tj) need = need || tri_tile(A, C, ti, tj, NTL, NTK);
+                        fa4[ti] = need ? M::load4(&sm.phi[(tri_row(A, ti, NTK) * 16 + l16) * SP + q * KQ + s0])
+                                       : f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+#pragma unroll
+                    for (int tj = 0; tj < TC; ++tj)
+                        fb4[tj] = (tri_tile(A, C, 0, tj, NTL, NTK) || tri_tile(A, C, 1, tj, NTL, NTK))
+                                      ? M::load4(grow[tj] + q * KQ + s0) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                            for (int tj = 0; tj < TC; ++tj)
+                                if (tri_tile(A, C, ti, tj, NTL, NTK))
+                                    acc[ti][tj] = M::mma(fa4[ti][e], fb4[tj][e], acc[ti][tj]);
+                }
+                } else {
 #pragma unroll
                 for (int k0 = 0; k0 < KP; k0 += M::KI) {
                     typename M::Frag fa[2], fb[TC];
@@ -699,27 +731,28 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                     for (int ti = 0; ti < 2; ++ti) {
                         bool need = false;
 #pragma unroll
-                        for (int tj = 0; tj < TC; ++tj) need = need || tri_tile(A, C, ti, tj, NTL);
-                        fa[ti] = need ? M::lds(&sm.phi[(tri_row(A, ti) * 16 + l16) * SP + (k0 + cq)])
+                        for (int tj = 0; tj < TC; ++tj) need = need || tri_tile(A, C, ti, tj, NTL, NTK);
+                        fa[ti] = need ? M::lds(&sm.phi[(tri_row(A, ti, NTK) * 16 + l16) * SP + (k0 + cq)])
                                       : M::zero_frag();
                     }
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj)
-                        fb[tj] = (tri_tile(A, C, 0, tj, NTL) || tri_tile(A, C, 1, tj, NTL))
+                        fb[tj] = (tri_tile(A, C, 0, tj, NTL, NTK) || tri_tile(A, C, 1, tj, NTL, NTK))
                                      ? M::lds(grow[tj] + (k0 + cq)) : M::zero_frag();
 #pragma unroll
                     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
                         for (int tj = 0; tj < TC; ++tj)
-                            if (tri_tile(A, C, ti, tj, NTL)) acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
+                            if (tri_tile(A, C, ti, tj, NTL, NTK)) acc[ti][tj] = M::mma(fa[ti], fb[tj], acc[ti][tj]);
+                }
                 }
                 if constexpr (!kComp) commit(nb);
 #pragma unroll
                 for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TC; ++tj) {
-                        if (!tri_tile(A, C, ti, tj, NTL)) continue;
-                        const int mt = tri_row(A, ti), nt = C + 2 * tj;
+                        if (!tri_tile(A, C, ti, tj, NTL, NTK)) continue;
+                        const int mt = tri_row(A, ti, NTK), nt = C + 2 * tj;
                         const int i = nt * 16 + l16;
                         const f32x4 gv = acc[ti][tj];
                         const f32x4 g2 = gv * gv;
@@ -739,15 +772,22 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
                                 __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x0), 0xB1, 0xF, 0xF, false));
                             const float y1 =
                                 __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x1), 0xB1, 0xF, 0xF, false));
-                            bf16x2 r0, r1;
-                            r0[0] = M::to_op(odd ? y0 : g2[0]);
-                            r0[1] = M::to_op(odd ? g2[2] : y0);
-                            r1[0] = M::to_op(odd ? y1 : g2[1]);
-                            r1[1] = M::to_op(odd ? g2[3] : y1);
                             const int j0 = mt * 16 + 4 * q + (odd ? 2 : 0);
                             const int c = (nt * 16 + (l16 & ~1)) ^ swz(j0);   // row j0 + 1: same permutation
-                            *reinterpret_cast<bf16x2*>(&sm.buf[j0 * SB + c]) = r0;
-                            *reinterpret_cast<bf16x2*>(&sm.buf[(j0 + 1) * SB + c]) = r1;
+                            if constexpr (M::EPL == 1) {
+                                const float2 r0 = {odd ? y0 : g2[0], odd ? g2[2] : y0};
+                                const float2 r1 = {odd ? y1 : g2[1], odd ? g2[3] : y1};
+                                *reinterpret_cast<float2*>(&sm.buf[j0 * SB + c]) = r0;
+                                *reinterpret_cast<float2*>(&sm.buf[(j0 + 1) * SB + c]) = r1;
+                            } else {
+                                bf16x2 r0, r1;
+                                r0[0] = M::to_op(odd ? y0 : g2[0]);
+                                r0[1] = M::to_op(odd ? g2[2] : y0);
+                                r1[0] = M::to_op(odd ? y1 : g2[1]);
+                                r1[1] = M::to_op(odd ? g2[3] : y1);
+                                *reinterpret_cast<bf16x2*>(&sm.buf[j0 * SB + c]) = r0;
+                                *reinterpret_cast<bf16x2*>(&sm.buf[(j0 + 1) * SB + c]) = r1;
+                            }
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     }
