@@ -393,7 +393,8 @@ __device__ __forceinline__ void sgd_body_t(const SgdArgs& g, const int r_id, Sgd
     // and the step is slower, so those keep the full product.  FP32: the
     // single-run kernels whose rows are read from global memory (k = 100, one
     // view: 31.3-31.6 -> 28.8-29.0 us; k = 128: 39.0 -> 35.8 us); the batched
-    // kernels, which also score restarts from G, keep the full product.
+    // kernels, which also score restarts from G, keep the full product (their
+    // three-view variants would spill, and one of them bounds a batched run).
     constexpr bool kTri = (M::EPL == 8 && WR == 4 && KP == 128 && NSTAGE <= 1 && !COMP && NTL == 7 && !SCORE) ||
                           (M::EPL == 1 && WR == 4 && (KP == 112 || KP == 128) && NSTAGE == 0 && !SCORE);
     const int swl = swz(l16);
